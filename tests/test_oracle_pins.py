@@ -1,0 +1,467 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these compares the oracle with itself: the references are exact
+rational brute force (a dense circulant operator, applied with Python
+integers / fractions), closed forms (Fourier modes, the FFT diagonalisation,
+binomial coefficients), invariants (constant fields, mass, the maximum
+principle, translation equivariance) and the values printed in the paper's
+worked example (tests/golden/paper_box9_m2.txt).
+"""
+
+import itertools
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_box9_m2.txt")
+EPS64 = 2.0 ** -53
+
+
+def read_golden(path=GOLDEN):
+    out = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split(":", 1)
+            out[k.strip()] = [float(t) for t in v.split()]
+    return out
+
+
+def brute_force(w, u0, T):
+    """A^T u0 with A the dense circulant correlation operator built as a
+    sparse matrix (aliased offsets summed into one entry), exact arithmetic
+    on Python ints / Fractions."""
+    shape = u0.shape
+    dim = len(shape)
+    r = (w.shape[0] - 1) // 2
+    rows = []
+    for x in itertools.product(*[range(n) for n in shape]):
+        row = {}
+        for o in itertools.product(range(-r, r + 1), repeat=dim):
+            wo = w[tuple(oi + r for oi in o)]
+            if wo == 0:
+                continue
+            col = tuple((xi + oi) % ni for xi, oi, ni in zip(x, o, shape))
+            c = int(np.ravel_multi_index(col, shape))
+            row[c] = row.get(c, 0) + wo
+        rows.append(row)
+    vec = list(u0.ravel())
+    for _ in range(T):
+        vec = [sum(wv * vec[c] for c, wv in row.items()) for row in rows]
+    return np.array(vec, dtype=object).reshape(shape)
+
+
+def exact(a):
+    return np.vectorize(lambda v: Fraction(float(v)), otypes=[object])(np.asarray(a))
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+SMALL_SHAPES = [
+    (1,), (2,), (3,), (5,), (7,), (12,),
+    (1, 1), (2, 3), (3, 3), (5, 2), (8, 9),
+    (1, 1, 1), (2, 3, 3), (4, 5, 6),
+]
+
+
+@pytest.mark.parametrize("shape", SMALL_SHAPES)
+@pytest.mark.parametrize("r", [1, 2])
+def test_brute_force_integer_bit_exact(shape, r):
+    dim = len(shape)
+    if dim == 3 and r == 2 and np.prod(shape) > 60:
+        pytest.skip("kept small")
+    g = rng(hash((shape, r)) % 2**32)
+    w = g.integers(-3, 4, size=(2 * r + 1,) * dim).astype(np.int64)
+    w[(r,) * dim] = 2
+    u0 = g.integers(0, 16, size=shape).astype(np.int64)
+    T = 3
+    ref = brute_force(w.astype(object), u0.astype(object), T)
+    got = oracle.sweep(w.astype(np.float64), u0.astype(np.float64), T)
+    assert np.all(np.abs(ref.astype(np.float64)) < 2 ** 53)
+    assert np.array_equal(got, ref.astype(np.float64))
+
+
+@pytest.mark.parametrize("shape", [(7,), (3, 5), (8, 9), (3, 4, 5)])
+def test_brute_force_float_within_bound(shape):
+    dim = len(shape)
+    g = rng(7 + len(shape))
+    w = g.random((3,) * dim)
+    w /= w.sum()
+    u0 = g.random(shape)
+    T = 4
+    ref = brute_force(exact(w), exact(u0), T)
+    got = oracle.sweep(w, u0, T)
+    taps = w.size
+    bound = 4 * T * taps * EPS64 * float(np.abs(w).sum()) ** T * float(np.abs(u0).max())
+    err = max(abs(Fraction(float(a)) - b) for a, b in zip(got.ravel(), ref.ravel()))
+    assert float(err) <= bound
+
+
+def test_brute_force_decimal_weights_rationals():
+    # the 2D heat stencil with exact decimal weights 3/5 and 1/10
+    w = np.zeros((3, 3), dtype=object)
+    w[1, 1] = Fraction(3, 5)
+    w[0, 1] = w[2, 1] = w[1, 0] = w[1, 2] = Fraction(1, 10)
+    u0 = rng(3).integers(0, 100, size=(6, 7))
+    T = 5
+    ref = brute_force(w, u0.astype(object), T)
+    got = oracle.sweep(synth.star2d_weights(0.6, 0.1), u0.astype(np.float64), T)
+    err = max(abs(Fraction(float(a)) - b) for a, b in zip(got.ravel(), ref.ravel()))
+    assert float(err) <= 8 * T * 5 * EPS64 * 100
+
+
+def fourier_closed_form(w, shape, k, T):
+    dim = len(shape)
+    r = (w.shape[0] - 1) // 2
+    lam = 0j
+    for o in itertools.product(range(-r, r + 1), repeat=dim):
+        wo = w[tuple(oi + r for oi in o)]
+        lam += wo * np.exp(2j * np.pi * sum(ki * oi / ni for ki, oi, ni in zip(k, o, shape)))
+    grids = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    phase = 2 * np.pi * sum(ki * gi / ni for ki, gi, ni in zip(k, grids, shape))
+    u0 = np.cos(phase)
+    uT = np.real(lam ** T * np.exp(1j * phase))
+    return u0, uT, lam
+
+
+@pytest.mark.parametrize("case", ["heat1d", "star2d", "star3d", "box2d_random"])
+def test_fourier_mode_decay(case):
+    if case == "heat1d":
+        w, shape, k = synth.heat1d_weights(), (96,), (5,)
+    elif case == "star2d":
+        w, shape, k = synth.star2d_weights(0.6, 0.1), (48, 40), (3, 7)
+    elif case == "star3d":
+        w, shape, k = synth.star3d_weights(0.4, 0.1), (12, 10, 8), (1, 2, 3)
+    else:
+        w, shape, k = synth.random_positive_weights(2, 1), (30, 26), (4, 3)
+    T = 40
+    u0, uT, lam = fourier_closed_form(w, shape, k, T)
+    if case == "heat1d":
+        assert abs(lam - math.cos(math.pi * k[0] / shape[0]) ** 2) < 1e-15
+    got = oracle.sweep(w, u0, T)
+    assert np.max(np.abs(got - uT)) < 1e-12
+
+
+def test_fft_closed_form_random_input():
+    shape = (32, 40)
+    w = synth.random_positive_weights(2, 1)
+    u0 = synth.grid_f64(shape)
+    T = 25
+    K = np.zeros(shape)
+    for oy in range(-1, 2):
+        for ox in range(-1, 2):
+            K[(-oy) % shape[0], (-ox) % shape[1]] += w[oy + 1, ox + 1]
+    lam = np.fft.fft2(K)
+    ref = np.real(np.fft.ifft2(np.fft.fft2(u0) * lam ** T))
+    got = oracle.sweep(w, u0, T)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_constant_field_dyadic_bit_exact(dim):
+    if dim == 1:
+        w, shape, c = synth.heat1d_weights(), (33,), 0.75
+    elif dim == 2:
+        w, shape, c = synth.star2d_weights(0.5, 0.125), (9, 11), 0.375
+    else:
+        w, shape, c = synth.star3d_weights(0.25, 0.125), (5, 4, 6), 0.625
+    got = oracle.sweep(w, np.full(shape, c), 60)
+    assert np.all(got == c)
+
+
+def test_constant_field_decimal_weights_bound():
+    T = 200
+    got = oracle.sweep(synth.star2d_weights(0.6, 0.1), np.full((8, 8), 0.5), T)
+    assert np.max(np.abs(got - 0.5)) <= T * 5 * 2 * EPS64 * 0.5 * 2
+
+
+@pytest.mark.parametrize("name", ["heat1d", "star2d", "box2d", "star3d", "box3d"])
+def test_mass_and_maximum_principle(name):
+    wl = synth.WORKLOADS[name]
+    shape = {1: (257,), 2: (37, 41), 3: (9, 10, 11)}[wl.dim]
+    u0 = synth.grid_f64(shape)
+    T = 30
+    got = oracle.sweep(wl.weights, u0, T)
+    sw = oracle.exact_sum(wl.weights)
+    expect = sw ** T * oracle.exact_sum(u0)
+    assert abs(oracle.exact_sum(got) - expect) <= 4 * T * wl.weights.size * EPS64 * oracle.exact_sum(np.abs(u0))
+    slack = 1e-12
+    assert got.min() >= u0.min() - slack and got.max() <= u0.max() + slack
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_translation_equivariance_bitwise(dim):
+    shape = {1: (50,), 2: (17, 23), 3: (7, 8, 9)}[dim]
+    w = synth.random_positive_weights(dim, 1)
+    u0 = synth.grid_f64(shape)
+    shift = {1: (5,), 2: (3, -4), 3: (1, 2, -3)}[dim]
+    axes = tuple(range(dim))
+    a = oracle.sweep(w, np.roll(u0, shift, axes), 9)
+    b = np.roll(oracle.sweep(w, u0, 9), shift, axes)
+    assert np.array_equal(a, b)
+
+
+# ----------------------------------------------------------------- fold pins
+
+def test_paper_worked_fold_example():
+    g = read_golden()
+    W2 = oracle.fold_weights(np.ones((3, 3)), 2)
+    lam = {1: np.array(g["lambda1"]), 2: np.array(g["lambda2"]), 3: np.array(g["lambda3"])}
+    assert np.array_equal(lam[2], 2 * lam[1]) and np.array_equal(lam[3], 3 * lam[1])
+    # column at horizontal offset t carries counterpart c - |t| (Eq. 5)
+    for j, n in enumerate(g["column_counterpart"]):
+        assert np.array_equal(W2[:, j], lam[int(n)])
+    assert np.array_equal(W2, np.outer(lam[1], lam[1]))
+    # counterpart count: distinct column vectors up to symmetry <= m + 1
+    distinct = {tuple(W2[:, j]) for j in range(W2.shape[1])}
+    assert len(distinct) <= int(g["max_counterparts"][0])
+    # counterpart reuse weights (Section 3.5): c2 = 2 c1, c3 = 0 c2 + 3 c1
+    c1, c2, c3 = W2[:, 0], W2[:, 1], W2[:, 2]
+    o2 = g["omega2"]
+    o3 = g["omega3"]
+    assert np.array_equal(c2, o2[0] * c1)
+    assert np.array_equal(c3, o3[0] * c2 + o3[1] * c1)
+
+
+def test_paper_profitability_counts():
+    g = read_golden()
+    naive, folded, ratio = oracle.collect_counts(np.ones((3, 3)), 2)
+    assert naive == g["collect_naive"][0]
+    assert folded == g["collect_folded"][0]
+    assert abs(ratio - g["profitable_index"][0]) < 1e-12
+
+
+@pytest.mark.parametrize("m", range(1, 11))
+def test_binomial_closed_form_heat1d(m):
+    W = oracle.fold_weights(synth.heat1d_weights(), m)
+    ref = np.array([math.comb(2 * m, m + j) / 4.0 ** m for j in range(-m, m + 1)])
+    assert np.array_equal(W, ref)
+
+
+@pytest.mark.parametrize("dim,m", [(1, 3), (2, 2), (2, 4), (3, 2)])
+def test_dft_identity(dim, m):
+    w = synth.random_positive_weights(dim, 1, offset=17)
+    Wm = oracle.fold_weights(w, m)
+    n = 2 * m + 5
+
+    def dft(arr, r):
+        K = np.zeros((n,) * dim)
+        for o in itertools.product(range(-r, r + 1), repeat=dim):
+            K[tuple((-oi) % n for oi in o)] += arr[tuple(oi + r for oi in o)]
+        return np.fft.fftn(K)
+
+    assert np.max(np.abs(dft(Wm, m) - dft(w, 1) ** m)) < 1e-13
+
+
+@pytest.mark.parametrize("name,m,count", [
+    ("star2d", 2, 13), ("star2d", 4, 41), ("star3d", 2, 25),
+    ("box3d", 2, 125), ("box2d", 4, 81), ("box2d", 8, 289)])
+def test_support_counts_and_mass(name, m, count):
+    w = synth.WORKLOADS[name].weights
+    Wm = oracle.fold_weights(w, m)
+    assert int(np.count_nonzero(Wm)) == count
+    assert abs(oracle.exact_sum(Wm) - oracle.exact_sum(w) ** m) < 1e-14
+
+
+def conv_full(a, b):
+    out = np.zeros(tuple(x + y - 1 for x, y in zip(a.shape, b.shape)), dtype=a.dtype)
+    for ia in itertools.product(*[range(n) for n in a.shape]):
+        if a[ia] == 0:
+            continue
+        sl = tuple(slice(i, i + n) for i, n in zip(ia, b.shape))
+        out[sl] += a[ia] * b
+    return out
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (1, 2), (2, 3)])
+def test_semigroup_integer_weights(a, b):
+    w = np.array([[1, 2, 0], [3, 5, 1], [0, 1, 2]], dtype=np.float64)
+    lhs = conv_full(oracle.fold_weights(w, a), oracle.fold_weights(w, b))
+    assert np.array_equal(lhs, oracle.fold_weights(w, a + b))
+
+
+def test_fold_m1_is_identity():
+    w = synth.random_positive_weights(3, 1)
+    assert np.array_equal(oracle.fold_weights(w, 1), w)
+
+
+def test_fold_identity_integer_exact():
+    w = np.ones((3, 3))
+    u0 = rng(11).integers(0, 16, size=(10, 12)).astype(np.float64)
+    for m, T in [(2, 4), (4, 4), (3, 6)]:
+        a = oracle.sweep(w, u0, T)
+        b = oracle.sweep(oracle.fold_weights(w, m), u0, T // m)
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,m", [("star2d", 4), ("box3d", 2), ("heat1d", 5)])
+def test_fold_identity_float_bound(name, m):
+    wl = synth.WORKLOADS[name]
+    shape = {1: (101,), 2: (30, 33), 3: (8, 9, 10)}[wl.dim]
+    u0 = synth.grid_f64(shape)
+    T = 4 * m
+    a = oracle.sweep(wl.weights, u0, T)
+    b = oracle.sweep(oracle.fold_weights(wl.weights, m), u0, T // m)
+    assert np.max(np.abs(a - b)) < 64 * T * EPS64 * 9 ** wl.dim
+
+
+# ------------------------------------------------------ precision readings
+
+@pytest.mark.parametrize("name,m", [("star2d", 1), ("star2d", 2), ("star2d", 4),
+                                    ("box2d", 8), ("box3d", 2), ("star3d", 2)])
+def test_fold_weights_f32_rounding(name, m):
+    w = synth.WORKLOADS[name].weights
+    Wm = oracle.fold_weights(w, m)
+    W32 = oracle.fold_weights_f32(w, m)
+    c = tuple([m] * w.ndim)
+    other = np.ones(Wm.shape, bool)
+    other[c] = False
+    assert np.array_equal(W32[other], Wm[other].astype(np.float32))
+    if m == 1:
+        assert np.array_equal(W32, w.astype(np.float32))
+    else:
+        target = oracle.exact_sum(w) ** m
+        s = oracle.exact_sum(W32.astype(np.float64))
+        ulp = np.spacing(np.float32(W32[c]))
+        assert abs(s - target) <= 0.5 * float(ulp) + 1e-15
+
+
+def frac_round_sig(x: float, bits: int) -> float:
+    """Round a float to ``bits`` significant bits, ties to even, with exact
+    rationals (independent of bit manipulation)."""
+    if x == 0:
+        return 0.0
+    f = Fraction(x)
+    e = math.floor(math.log2(abs(x)))
+    while Fraction(2) ** e > abs(f):
+        e -= 1
+    while Fraction(2) ** (e + 1) <= abs(f):
+        e += 1
+    q = f / Fraction(2) ** (e - bits + 1)
+    fl = math.floor(q)
+    rem = q - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    return float(fl * Fraction(2) ** (e - bits + 1))
+
+
+def test_bf16_rounding_against_rationals():
+    vals = np.concatenate([
+        np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -9, -0.1, 0.6, 3.0e-5], dtype=np.float32),
+        synth.uniform_f32(5, 9, 2000) * np.float32(4) - np.float32(2),
+    ]).astype(np.float32)
+    got = oracle.bf16_rne(vals)
+    ref = np.array([frac_round_sig(float(v), 8) for v in vals], dtype=np.float32)
+    assert np.array_equal(got, ref)
+    assert got[1] == 1.0 and got[2] == np.float32(1 + 2 ** -6)
+    hi, lo = oracle.bf16_split(vals)
+    assert np.array_equal(hi, got)
+    resid = vals.astype(np.float64) - hi.astype(np.float64) - lo.astype(np.float64)
+    assert np.all(np.abs(resid) <= np.abs(vals.astype(np.float64)) * 2.0 ** -16)
+
+
+def test_schedule_reading():
+    assert oracle.schedule(1000, 4) == (250, 0)
+    assert oracle.schedule(50, 4) == (12, 2)
+    assert oracle.schedule(7, 1) == (7, 0)
+    assert oracle.schedule(0, 3) == (0, 0)
+
+
+# ---------------------------------------------------------- FP32 mirror pins
+
+def test_f32_mirror_integer_exact_and_close():
+    g = rng(5)
+    w = g.integers(-2, 3, size=(3, 3)).astype(np.float32)
+    u0 = g.integers(0, 8, size=(9, 7)).astype(np.float32)
+    ref = brute_force(w.astype(np.int64).astype(object), u0.astype(np.int64).astype(object), 3)
+    got = oracle.sweep_f32(w, u0, 3)
+    assert np.array_equal(got, ref.astype(np.float32))
+    wl = synth.WORKLOADS["box2d"]
+    u = synth.grid_f32((40, 44))
+    a = oracle.sweep_f32(wl.weights.astype(np.float32), u, 50)
+    b = oracle.sweep(wl.weights, u.astype(np.float64), 50)
+    assert oracle.errors(a, b)["e_rel"] < 50 * 9 * 2.0 ** -24
+
+
+def test_f32_mirror_matches_explicit_fmaf_chain():
+    # one step evaluated with a literal per-tap fused multiply-add chain in
+    # exact rationals rounded to FP32 after every tap
+    w = synth.WORKLOADS["box2d"].weights.astype(np.float32)
+    u0 = synth.grid_f32((5, 6))
+    got = oracle.sweep_f32(w, u0, 1)
+    for y in range(5):
+        for x in range(6):
+            acc = np.float32(0.0)
+            for oy in range(-1, 2):
+                for ox in range(-1, 2):
+                    exact_v = (Fraction(float(w[oy + 1, ox + 1]))
+                               * Fraction(float(u0[(y + oy) % 5, (x + ox) % 6]))
+                               + Fraction(float(acc)))
+                    acc = np.float32(round_exact_to_f32(exact_v))
+            assert got[y, x] == acc
+
+
+def round_exact_to_f32(q: Fraction) -> float:
+    if q == 0:
+        return 0.0
+    sign = -1 if q < 0 else 1
+    a = abs(q)
+    e = 0
+    while Fraction(2) ** e > a:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= a:
+        e += 1
+    scale = Fraction(2) ** (e - 23)
+    t = a / scale
+    fl = math.floor(t)
+    rem = t - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    return sign * float(fl * scale)
+
+
+def test_sweep_window_matches_full_grid_bitwise():
+    wl = synth.WORKLOADS["star2d"]
+    u0 = synth.grid_f32((64, 80))
+    T = 6
+    full = oracle.sweep_f32(wl.weights.astype(np.float32), u0, T)
+    pts = [(0, 0), (63, 79), (10, 40), (32, 1)]
+    got = oracle.sweep_window(wl.weights.astype(np.float32), u0, T, pts, f32=True)
+    assert np.array_equal(got, np.array([full[p] for p in pts]))
+    full64 = oracle.sweep(wl.weights, u0.astype(np.float64), T)
+    got64 = oracle.sweep_window(wl.weights, u0.astype(np.float64), T, pts)
+    assert np.array_equal(got64, np.array([full64[p] for p in pts]))
+
+
+# ------------------------------------------------- planted-mistake checks
+
+def test_pins_catch_orientation_and_transpose_mistakes():
+    """A flipped offset (u[x-o] instead of u[x+o]) or transposed weights give
+    different values than the exact brute force for an asymmetric stencil."""
+    g = rng(9)
+    w = g.integers(1, 5, size=(3, 3)).astype(np.float64)
+    u0 = g.integers(0, 9, size=(5, 6)).astype(np.float64)
+    ref = brute_force(w.astype(np.int64).astype(object), u0.astype(np.int64).astype(object), 2).astype(np.float64)
+    assert np.array_equal(oracle.sweep(w, u0, 2), ref)
+    assert not np.array_equal(oracle.sweep(w[::-1, ::-1].copy(), u0, 2), ref)
+    assert not np.array_equal(oracle.sweep(w.T.copy(), u0, 2), ref)
+
+
+def test_pins_catch_dropped_fold_term():
+    W = oracle.fold_weights(np.ones((3, 3)), 2)
+    bad = W.copy()
+    bad[0, 0] = 0.0
+    u0 = rng(2).integers(0, 10, size=(8, 8)).astype(np.float64)
+    good = oracle.sweep(np.ones((3, 3)), u0, 2)
+    assert np.array_equal(oracle.sweep(W, u0, 1), good)
+    assert not np.array_equal(oracle.sweep(bad, u0, 1), good)
