@@ -1,0 +1,205 @@
+/*
+ * stencil.h -- C ABI of libstencil.so: iterated constant-coefficient stencil
+ * sweeps with temporal computation folding on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Li et al., "Reducing Redundancy in Data Organization and Arithmetic
+ * Calculation for Stencil Computations" (arXiv 2103.09235).
+ *  - The stencil (Section 1): every point of a d-dimensional grid at time
+ *    t+1 is a weighted sum of itself and its neighbours at time t; time is
+ *    the outermost loop.
+ *  - Temporal computation folding (Section 3.1, Section 3.3, Eq. 4-6): m
+ *    consecutive steps are replaced by one application of the m-step
+ *    operator whose reassigned weights W_m are the m-fold self-convolution of
+ *    the stencil's weights (the paper's "folding matrix").
+ *
+ * Conventions used by every entry point:
+ *  - Update rule (correlation form): u_{t+1}[x] = sum_o w[o] * u_t[(x+o) mod n]
+ *    per axis, periodic boundaries.
+ *  - Weights are a dense FP64 array of (2r+1)^dim values in row-major order,
+ *    indexed [r+oz][r+oy][r+ox] (x = last axis, fastest).
+ *  - Grids are contiguous row-major device arrays, x fastest, no padding;
+ *    shape[] lists the axes slowest first (numpy order).
+ *  - All pointers named "device" are HIP device pointers owned by the caller;
+ *    the library never frees caller memory.  Work is enqueued asynchronously
+ *    on the caller's HIP stream (NULL = the null stream).
+ *  - Every function returns STENCIL_OK (0) or a negative status; on failure
+ *    nothing has been enqueued and stencil_last_error() describes the cause.
+ *    No C++ exception or abort crosses this interface.
+ *  - A plan must not be changed (fold, mode) while work using it is still in
+ *    flight on a stream.  Plans are not thread-safe; distinct plans are.
+ */
+#ifndef STENCIL_H_
+#define STENCIL_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stencil_plan_s *stencil_plan; /* opaque, library-owned */
+
+enum { STENCIL_STAR = 0, STENCIL_BOX = 1 };           /* stencil shape       */
+enum { STENCIL_PERIODIC = 0, STENCIL_DIRICHLET = 1 }; /* boundary            */
+enum { STENCIL_F32 = 0, STENCIL_F64 = 1 };            /* grid element type   */
+enum {
+  STENCIL_MODE_VECTOR = 0,      /* tiled vector kernels (default)            */
+  STENCIL_MODE_EXACT_ORDER = 1, /* one thread per point, canonical order     */
+  STENCIL_MODE_MFMA_BF16X3 = 2  /* 2D box folds as BF16 hi+lo MFMA products  */
+};
+enum {
+  STENCIL_OK = 0,
+  STENCIL_E_ARG = -1,         /* invalid argument                           */
+  STENCIL_E_UNSUPPORTED = -2, /* valid but not supported by this library    */
+  STENCIL_E_NOMEM = -3,       /* device or host allocation failed           */
+  STENCIL_E_DEVICE = -4,      /* HIP runtime error (message in last_error)  */
+  STENCIL_E_STATE = -5        /* call out of order (e.g. no plan weights)   */
+};
+
+typedef struct {
+  void *data;       /* device, caller-owned; input u_0, result u_T lands here */
+  void *scratch;    /* device, caller-owned, same byte size as data and not
+                       overlapping it; or NULL = plan-owned cached scratch   */
+  int dtype;        /* STENCIL_F32 or STENCIL_F64                             */
+  int dim;          /* must equal the plan's dim                              */
+  int64_t shape[3]; /* first dim entries used, slowest axis first             */
+  void *stream;     /* hipStream_t or NULL                                    */
+} stencil_grid;
+
+typedef struct {
+  int autotune;           /* 1 = time candidate configurations and cache the
+                             winner; 0 = cached choice or the default        */
+  const char *tune_cache; /* cache file path; NULL = $STENCIL_TUNE_CACHE, or
+                             no file                                          */
+  int use_graph;          /* 1 = capture the launches of the time loop in one
+                             hipGraph and replay it                           */
+  int max_m;              /* largest fold depth the tuner may choose (>= 1)   */
+  int *chosen_m;          /* out, nullable: count entries, fold depth used    */
+} stencil_batch_opts;
+
+/*
+ * stencil_plan_create -- validate and copy a stencil (Section 1; the Table 1
+ * families are 1D/2D/3D star and box stencils).
+ *   dim      1, 2 or 3.
+ *   radius   r >= 1.
+ *   shape    STENCIL_STAR (weights off the axes must be zero) or STENCIL_BOX.
+ *   weights  host, (2r+1)^dim finite FP64 values, copied (the caller may free
+ *            them on return).
+ *   boundary STENCIL_PERIODIC; STENCIL_DIRICHLET returns E_UNSUPPORTED.
+ *   out      receives the plan; the plan starts unfolded (m = 1) in
+ *            STENCIL_MODE_VECTOR.
+ * Errors: E_ARG for a bad argument, E_UNSUPPORTED, E_NOMEM.  No device work.
+ */
+int stencil_plan_create(int dim, int radius, int shape, const double *weights,
+                        int boundary, stencil_plan *out);
+
+/*
+ * stencil_fold_weights -- set the plan's fold depth m and form W_m, the
+ * m-fold self-convolution of the weights (Section 3.3, Eq. 4-6: merged terms
+ * of the m-step expansion with reassigned weights), in FP64 on the current
+ * GPU.  W_m has (2mr+1)^dim entries; its sum is (sum w)^m.
+ *   m            >= 1; m = 1 means the plain sweep.
+ *   out_or_null  host, nullable; if given, receives W_m (FP64, row-major).
+ *   out_len      host, nullable; receives (2mr+1)^dim.
+ * The FP32 weights used by FP32 grids are W_m rounded to nearest (for m >= 2
+ * the centre is set so that their FP64 sum is (sum w)^m to FP32 rounding);
+ * see stencil_fold_weights_f32.  Synchronous (copies W_m to the host).
+ * Errors: E_ARG, E_UNSUPPORTED (m too large), E_DEVICE, E_NOMEM.
+ */
+int stencil_fold_weights(stencil_plan p, int m, double *out_or_null,
+                         int64_t *out_len);
+
+/*
+ * stencil_fold_weights_f32 -- the FP32 weights the plan's FP32 kernels use
+ * for its current fold depth.  out: host, (2mr+1)^dim floats, nullable;
+ * out_len: nullable.  Errors: E_ARG.  No device work.
+ */
+int stencil_fold_weights_f32(stencil_plan p, float *out, int64_t *out_len);
+
+/*
+ * stencil_plan_set_mode -- choose the kernel family (STENCIL_MODE_*).
+ * MFMA_BF16X3 requires a 2D plan; runs with it accept FP32 grids only.
+ * Errors: E_ARG, E_UNSUPPORTED.
+ */
+int stencil_plan_set_mode(stencil_plan p, int mode);
+
+/*
+ * stencil_plan_info -- read back plan parameters (any pointer may be NULL):
+ * dimension, radius r, fold depth m, folded radius m*r, mode.
+ */
+int stencil_plan_info(stencil_plan p, int *dim, int *radius, int *m,
+                      int *folded_radius, int *mode);
+
+/*
+ * stencil_profitability -- scalar profitability analysis (Section 3.2,
+ * Eq. 1-3) for fold depth m, by enumeration of the stencil's support S:
+ *   naive  = |S| * sum_{j=0}^{m-1} |S^(+j)|  (S^(+j) = j-fold sum set,
+ *            S^(+0) = {0}): one |S|-way weighted sum per distinct point of
+ *            each intermediate level of the m-step expansion;
+ *   folded = |S^(+m)|: one term per point of the folded stencil.
+ * The profitable index is naive / folded (2D 9-point box, m = 2: 90 / 25).
+ * Errors: E_ARG.  No device work.
+ */
+int stencil_profitability(stencil_plan p, int m, int64_t *naive,
+                          int64_t *folded);
+
+/*
+ * stencil_run -- advance a grid by T original time steps (Section 1; time
+ * outermost, two arrays alternating between odd and even steps as in the
+ * Jacobi scheme of Section 3.3).  With fold depth m the library runs
+ * floor(T/m) folded sweeps of W_m (halo width m*r) and then T mod m plain
+ * sweeps; if the number of sweeps is odd a final device copy puts the result
+ * back into g->data.
+ *   g->dtype F32 or F64 (MFMA mode: F32 only); g->dim must equal the plan's;
+ *   every axis >= 2*m*r + 1 (else E_UNSUPPORTED).  T = 0 is a no-op; T < 0
+ *   is E_ARG.  g->scratch, when given, must not overlap g->data.
+ * Enqueued asynchronously on g->stream; the caller keeps data and scratch
+ * alive until that work has completed.
+ * Errors: E_ARG, E_UNSUPPORTED, E_STATE, E_NOMEM, E_DEVICE.
+ */
+int stencil_run(stencil_plan p, stencil_grid *g, int64_t T);
+
+/*
+ * stencil_run_batched -- advance count independent 2D grids by T steps each,
+ * grids[i] with plans[i] (plans may repeat; every plan must be 2D), with one
+ * persistent launch per (folded) sweep over all grids together and, when
+ * opts->use_graph, the whole time loop captured in one hipGraph on
+ * grids[0].stream (all grids must name the same stream).  Every grid needs a
+ * caller scratch buffer.  The fold depth of each plan is chosen per
+ * (stencil, size class) by timing candidates when opts->autotune (largest
+ * opts->max_m), else taken from the cache or set to 1; the plans' own fold
+ * depth is not changed.  opts may be NULL (no tuning, no graph, m = 1).
+ * Errors: E_ARG, E_UNSUPPORTED, E_NOMEM, E_DEVICE.
+ */
+int stencil_run_batched(const stencil_plan *plans, stencil_grid *grids,
+                        int count, int64_t T, const stencil_batch_opts *opts);
+
+/*
+ * stencil_residual -- FP64 Neumaier-compensated reductions on the GPU, for the
+ * mass and long-horizon residual checks:
+ *   out[0] = sum_i u[i]; out[1] = sum_i |u[i] - ref[i]|;
+ *   out[2] = max_i |u[i] - ref[i]|  (out[1], out[2] are 0 when ref is NULL).
+ *   u, ref: device arrays of n elements of dtype; out: host, 3 doubles.
+ * Synchronous on stream.  The result is deterministic (fixed reduction tree).
+ * Errors: E_ARG, E_NOMEM, E_DEVICE.
+ */
+int stencil_residual(const void *u, const void *ref, int dtype, int64_t n,
+                     void *stream, double *out);
+
+/* stencil_plan_destroy -- free the plan and everything it owns (weights,
+ * cached scratch, graphs).  NULL is ignored.  The caller must ensure no work
+ * using the plan is still in flight. */
+void stencil_plan_destroy(stencil_plan p);
+
+/* stencil_last_error -- thread-local description of the last failure on
+ * this thread ("" if none).  Valid until the next call on this thread. */
+const char *stencil_last_error(void);
+
+/* stencil_version -- library version string. */
+const char *stencil_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STENCIL_H_ */

@@ -1,0 +1,447 @@
+// C ABI of libstencil.so: plan management, validation, the time loop and
+// its buffer parity.  Every entry point validates before any device work and
+// returns a status; no exception leaves this file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace stencil {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? STENCIL_E_NOMEM : STENCIL_E_DEVICE;
+}
+
+namespace {
+
+constexpr int kMaxFoldedRadius = 64;
+constexpr int64_t kMaxWeights = 1 << 20;
+
+size_t esize(int dtype) { return dtype == STENCIL_F64 ? 8 : 4; }
+
+bool on_axes(int64_t idx, int dim, int r) {
+  const int s = 2 * r + 1;
+  int nonzero = 0;
+  for (int a = 0; a < dim; ++a) {
+    if ((int)(idx % s) != r) ++nonzero;
+    idx /= s;
+  }
+  return nonzero <= 1;
+}
+
+void free_operator(OperatorDev &op) {
+  if (op.w_dev) (void)hipFree(op.w_dev);
+  if (op.taps_dev) (void)hipFree(op.taps_dev);
+  op = OperatorDev();
+}
+
+void free_device_state(DeviceState &d) {
+  free_operator(d.plain32);
+  free_operator(d.plain64);
+  free_operator(d.fold32);
+  free_operator(d.fold64);
+  for (auto &kv : d.graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto &kv : d.graph_src) (void)hipGraphDestroy(kv.second);
+  d.graphs.clear();
+  d.graph_src.clear();
+  if (d.scratch) (void)hipFree(d.scratch);
+  d.scratch = nullptr;
+  d.scratch_bytes = 0;
+  d.ready32 = d.ready64 = false;
+  d.ready_m = 0;
+}
+
+// Build one operator on the current device from dense host weights.
+template <typename T>
+int build_operator(const std::vector<T> &w, int dim, int R, int mask,
+                   OperatorDev &op) {
+  free_operator(op);
+  op.R = R;
+  op.mask = mask;
+  const int s = 2 * R + 1;
+  std::vector<int4> taps;
+  for (int64_t i = 0; i < (int64_t)w.size(); ++i) {
+    if (w[i] == T(0)) continue;
+    int o[3] = {0, 0, 0};
+    int64_t t = i;
+    for (int a = dim - 1; a >= 0; --a) {
+      o[3 - dim + a] = (int)(t % s) - R;
+      t /= s;
+    }
+    taps.push_back(int4{o[0], o[1], o[2], (int)i});
+  }
+  op.ntaps = (int)taps.size();
+  STENCIL_HIP_TRY(hipMalloc(&op.w_dev, sizeof(T) * w.size()));
+  STENCIL_HIP_TRY(hipMemcpy(op.w_dev, w.data(), sizeof(T) * w.size(),
+                            hipMemcpyHostToDevice));
+  STENCIL_HIP_TRY(hipMalloc(&op.taps_dev, sizeof(int4) * std::max<size_t>(1, taps.size())));
+  if (!taps.empty())
+    STENCIL_HIP_TRY(hipMemcpy(op.taps_dev, taps.data(), sizeof(int4) * taps.size(),
+                              hipMemcpyHostToDevice));
+  if constexpr (sizeof(T) == 4) {
+    op.w32.assign(w.begin(), w.end());
+  } else {
+    op.w64.assign(w.begin(), w.end());
+  }
+  return STENCIL_OK;
+}
+
+// Operators for the current fold depth and dtype on the current device.
+int ensure_operators(stencil_plan p, int device, int dtype) {
+  DeviceState &d = p->dev[device];
+  if (d.ready_m != p->m) {
+    d.ready32 = d.ready64 = false;
+    d.ready_m = p->m;
+  }
+  const int R = p->m * p->r;
+  if (dtype == STENCIL_F32 && !d.ready32) {
+    std::vector<float> w32(p->w.size());
+    for (size_t i = 0; i < w32.size(); ++i) w32[i] = (float)p->w[i];
+    int rc = build_operator(w32, p->dim, p->r, mask_for(p->shape, 1), d.plain32);
+    if (rc) return rc;
+    rc = build_operator(p->Wm32, p->dim, R, mask_for(p->shape, p->m), d.fold32);
+    if (rc) return rc;
+    d.ready32 = true;
+  }
+  if (dtype == STENCIL_F64 && !d.ready64) {
+    int rc = build_operator(p->w, p->dim, p->r, mask_for(p->shape, 1), d.plain64);
+    if (rc) return rc;
+    rc = build_operator(p->Wm, p->dim, R, mask_for(p->shape, p->m), d.fold64);
+    if (rc) return rc;
+    d.ready64 = true;
+  }
+  return STENCIL_OK;
+}
+
+hipError_t dispatch(stencil_plan p, const SweepLaunch &L) {
+  if (p->mode == STENCIL_MODE_EXACT_ORDER) return launch_naive(L);
+  hipError_t e = hipErrorNotSupported;
+  if (L.g.dim == 1) e = launch_sweep1d(L);
+  else if (L.g.dim == 2) e = launch_sweep2d(L);
+  else e = launch_sweep3d(L);
+  if (e == hipErrorNotSupported) {
+    if (L.steps != 1) return hipErrorNotSupported;
+    (void)hipGetLastError();
+    e = launch_naive(L);
+  }
+  return e;
+}
+
+int check_plan(stencil_plan p) {
+  if (!p) return fail(STENCIL_E_ARG, "plan is NULL");
+  return STENCIL_OK;
+}
+
+}  // namespace
+
+}  // namespace stencil
+
+using namespace stencil;
+
+extern "C" {
+
+const char *stencil_last_error(void) { return g_last_error.c_str(); }
+
+const char *stencil_version(void) { return "stencilfold 0.1.0 (gfx950)"; }
+
+int stencil_plan_create(int dim, int radius, int shape, const double *weights,
+                        int boundary, stencil_plan *out) {
+  set_error("");
+  if (!out) return fail(STENCIL_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (dim < 1 || dim > 3) return fail(STENCIL_E_ARG, "dim must be 1, 2 or 3");
+  if (radius < 1) return fail(STENCIL_E_ARG, "radius must be >= 1");
+  if (radius > kMaxFoldedRadius)
+    return fail(STENCIL_E_UNSUPPORTED, "radius too large");
+  if (shape != STENCIL_STAR && shape != STENCIL_BOX)
+    return fail(STENCIL_E_ARG, "shape must be STENCIL_STAR or STENCIL_BOX");
+  if (boundary != STENCIL_PERIODIC && boundary != STENCIL_DIRICHLET)
+    return fail(STENCIL_E_ARG, "boundary must be PERIODIC or DIRICHLET");
+  if (!weights) return fail(STENCIL_E_ARG, "weights is NULL");
+  const int64_t n = count_of(dim, radius);
+  if (n > kMaxWeights) return fail(STENCIL_E_UNSUPPORTED, "stencil too large");
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(weights[i])) return fail(STENCIL_E_ARG, "weights must be finite");
+    if (shape == STENCIL_STAR && weights[i] != 0.0 && !on_axes(i, dim, radius))
+      return fail(STENCIL_E_ARG, "STAR stencil has a nonzero weight off the axes");
+  }
+  if (boundary == STENCIL_DIRICHLET)
+    return fail(STENCIL_E_UNSUPPORTED, "only periodic boundaries are implemented");
+  stencil_plan p = new (std::nothrow) stencil_plan_s();
+  if (!p) return fail(STENCIL_E_NOMEM, "plan allocation failed");
+  try {
+    p->dim = dim;
+    p->r = radius;
+    p->shape = shape;
+    p->boundary = boundary;
+    p->w.assign(weights, weights + n);
+    p->m = 1;
+    p->Wm = p->w;
+    round_fold_f32(p->w, p->Wm, dim, radius, 1, p->Wm32);
+    p->Wm_hi.resize(n);
+    p->Wm_lo.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+      p->Wm_hi[i] = bf16_rne(p->Wm32[i]);
+      float hi;
+      uint32_t b = (uint32_t)p->Wm_hi[i] << 16;
+      std::memcpy(&hi, &b, 4);
+      p->Wm_lo[i] = bf16_rne(p->Wm32[i] - hi);
+    }
+  } catch (...) {
+    delete p;
+    return fail(STENCIL_E_NOMEM, "plan allocation failed");
+  }
+  *out = p;
+  return STENCIL_OK;
+}
+
+int stencil_fold_weights(stencil_plan p, int m, double *out_or_null,
+                         int64_t *out_len) {
+  set_error("");
+  if (int rc = check_plan(p)) return rc;
+  if (m < 1) return fail(STENCIL_E_ARG, "m must be >= 1");
+  if ((int64_t)m * p->r > kMaxFoldedRadius)
+    return fail(STENCIL_E_UNSUPPORTED, "folded radius m*r too large");
+  const int R = m * p->r;
+  const int64_t n = count_of(p->dim, R);
+  if (n > kMaxWeights) return fail(STENCIL_E_UNSUPPORTED, "folded stencil too large");
+  std::vector<double> Wm;
+  std::vector<float> W32;
+  std::vector<uint16_t> hi(n), lo(n);
+  try {
+    int rc = fold_on_device(p->w, p->dim, p->r, m, Wm);
+    if (rc) return rc;
+    round_fold_f32(p->w, Wm, p->dim, R, m, W32);
+    for (int64_t i = 0; i < n; ++i) {
+      hi[i] = bf16_rne(W32[i]);
+      float h;
+      uint32_t b = (uint32_t)hi[i] << 16;
+      std::memcpy(&h, &b, 4);
+      lo[i] = bf16_rne(W32[i] - h);
+    }
+  } catch (...) {
+    return fail(STENCIL_E_NOMEM, "host allocation failed");
+  }
+  p->m = m;
+  p->Wm.swap(Wm);
+  p->Wm32.swap(W32);
+  p->Wm_hi.swap(hi);
+  p->Wm_lo.swap(lo);
+  if (out_or_null) std::memcpy(out_or_null, p->Wm.data(), sizeof(double) * n);
+  if (out_len) *out_len = n;
+  return STENCIL_OK;
+}
+
+int stencil_fold_weights_f32(stencil_plan p, float *out, int64_t *out_len) {
+  set_error("");
+  if (int rc = check_plan(p)) return rc;
+  if (out) std::memcpy(out, p->Wm32.data(), sizeof(float) * p->Wm32.size());
+  if (out_len) *out_len = (int64_t)p->Wm32.size();
+  return STENCIL_OK;
+}
+
+int stencil_plan_set_mode(stencil_plan p, int mode) {
+  set_error("");
+  if (int rc = check_plan(p)) return rc;
+  if (mode != STENCIL_MODE_VECTOR && mode != STENCIL_MODE_EXACT_ORDER &&
+      mode != STENCIL_MODE_MFMA_BF16X3)
+    return fail(STENCIL_E_ARG, "unknown mode");
+  if (mode == STENCIL_MODE_MFMA_BF16X3 && p->dim != 2)
+    return fail(STENCIL_E_UNSUPPORTED, "MFMA mode needs a 2D plan");
+  p->mode = mode;
+  return STENCIL_OK;
+}
+
+int stencil_plan_info(stencil_plan p, int *dim, int *radius, int *m,
+                      int *folded_radius, int *mode) {
+  set_error("");
+  if (int rc = check_plan(p)) return rc;
+  if (dim) *dim = p->dim;
+  if (radius) *radius = p->r;
+  if (m) *m = p->m;
+  if (folded_radius) *folded_radius = p->m * p->r;
+  if (mode) *mode = p->mode;
+  return STENCIL_OK;
+}
+
+int stencil_profitability(stencil_plan p, int m, int64_t *naive, int64_t *folded) {
+  set_error("");
+  if (int rc = check_plan(p)) return rc;
+  if (m < 1) return fail(STENCIL_E_ARG, "m must be >= 1");
+  if ((int64_t)m * p->r > kMaxFoldedRadius)
+    return fail(STENCIL_E_UNSUPPORTED, "m*r too large");
+  try {
+    profitability(p->w, p->dim, p->r, m, naive, folded);
+  } catch (...) {
+    return fail(STENCIL_E_NOMEM, "host allocation failed");
+  }
+  return STENCIL_OK;
+}
+
+int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
+  set_error("");
+  if (int rc = check_plan(p)) return rc;
+  if (!g) return fail(STENCIL_E_ARG, "grid is NULL");
+  if (T < 0) return fail(STENCIL_E_ARG, "T must be >= 0");
+  if (g->dim != p->dim) return fail(STENCIL_E_ARG, "grid dim differs from plan dim");
+  if (g->dtype != STENCIL_F32 && g->dtype != STENCIL_F64)
+    return fail(STENCIL_E_ARG, "dtype must be STENCIL_F32 or STENCIL_F64");
+  if (!g->data) return fail(STENCIL_E_ARG, "data is NULL");
+  if (p->mode == STENCIL_MODE_MFMA_BF16X3 && g->dtype != STENCIL_F32)
+    return fail(STENCIL_E_UNSUPPORTED, "MFMA mode takes FP32 grids only");
+  Geom geo;
+  geo.dim = p->dim;
+  int64_t n[3] = {1, 1, 1};
+  for (int a = 0; a < p->dim; ++a) {
+    if (g->shape[a] < 1) return fail(STENCIL_E_ARG, "grid axes must be >= 1");
+    n[3 - p->dim + a] = g->shape[a];
+  }
+  geo.nz = n[0];
+  geo.ny = n[1];
+  geo.nx = n[2];
+  const int64_t need = 2 * (int64_t)p->m * p->r + 1;
+  for (int a = 0; a < p->dim; ++a)
+    if (g->shape[a] < need)
+      return fail(STENCIL_E_UNSUPPORTED,
+                  "every grid axis must be >= 2*m*r+1 for this plan");
+  if (geo.count() > ((int64_t)1 << 40)) return fail(STENCIL_E_UNSUPPORTED, "grid too large");
+  const size_t bytes = (size_t)geo.count() * esize(g->dtype);
+  if (g->scratch) {
+    const char *a = (const char *)g->data, *b = (const char *)g->scratch;
+    if (a < b + bytes && b < a + bytes)
+      return fail(STENCIL_E_ARG, "data and scratch overlap");
+  }
+  if (T == 0) return STENCIL_OK;
+
+  int device = 0;
+  STENCIL_HIP_TRY(hipGetDevice(&device));
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, g->data) != hipSuccess ||
+      attr.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(STENCIL_E_ARG, "data is not a device pointer");
+  }
+  if (int rc = ensure_operators(p, device, g->dtype)) return rc;
+  DeviceState &d = p->dev[device];
+  void *scratch = g->scratch;
+  if (!scratch) {
+    if (d.scratch_bytes < bytes) {
+      if (d.scratch) {
+        STENCIL_HIP_TRY(hipDeviceSynchronize());
+        (void)hipFree(d.scratch);
+        d.scratch = nullptr;
+        d.scratch_bytes = 0;
+      }
+      STENCIL_HIP_TRY(hipMalloc(&d.scratch, bytes));
+      d.scratch_bytes = bytes;
+    }
+    scratch = d.scratch;
+  }
+  const OperatorDev *plain = g->dtype == STENCIL_F32 ? &d.plain32 : &d.plain64;
+  const OperatorDev *folded = g->dtype == STENCIL_F32 ? &d.fold32 : &d.fold64;
+  const int64_t q = p->m > 1 ? T / p->m : 0;
+  const int64_t s = p->m > 1 ? T % p->m : T;
+
+  // Work list: (operator, applications).  Tiled kernels may fuse several
+  // applications of one operator per launch (1D temporal blocking).
+  struct Pass { const OperatorDev *op; int64_t apps; };
+  Pass passes[2] = {{folded, q}, {plain, s}};
+  SweepLaunch L;
+  L.g = geo;
+  L.dtype = g->dtype;
+  L.stream = (hipStream_t)g->stream;
+  // Launch counts per pass, then parity: an odd total leaves the result in
+  // scratch and costs a final copy, unless a fusing pass can split once more.
+  int64_t launches[2] = {0, 0};
+  int64_t kmax[2] = {1, 1};
+  for (int i = 0; i < 2; ++i) {
+    if (passes[i].apps == 0) continue;
+    L.op = passes[i].op;
+    kmax[i] = (p->mode == STENCIL_MODE_EXACT_ORDER || p->dim != 1) ? 1
+              : std::max(1, sweep1d_max_steps(L));
+    launches[i] = (passes[i].apps + kmax[i] - 1) / kmax[i];
+  }
+  for (int i = 0; i < 2; ++i) {
+    if ((launches[0] + launches[1]) % 2 == 0) break;
+    if (kmax[i] > 1 && launches[i] < passes[i].apps) launches[i] += 1;
+  }
+  const void *src = g->data;
+  void *dst = scratch;
+  for (int i = 0; i < 2; ++i) {
+    if (passes[i].apps == 0) continue;
+    L.op = passes[i].op;
+    int64_t left = passes[i].apps;
+    for (int64_t k = 0; k < launches[i]; ++k) {
+      const int64_t take = (left + (launches[i] - k) - 1) / (launches[i] - k);
+      L.in = src;
+      L.out = dst;
+      L.steps = (int)take;
+      hipError_t e = dispatch(p, L);
+      if (e != hipSuccess) return hip_fail(e, "sweep launch");
+      left -= take;
+      const void *t = src;
+      src = dst;
+      dst = const_cast<void *>(t);
+    }
+  }
+  if (src != g->data) {
+    hipError_t e = launch_copy(src, g->data, (int64_t)bytes, L.stream);
+    if (e != hipSuccess) return hip_fail(e, "final copy");
+  }
+  return STENCIL_OK;
+}
+
+int stencil_residual(const void *u, const void *ref, int dtype, int64_t n,
+                     void *stream, double *out) {
+  set_error("");
+  if (!u || !out) return fail(STENCIL_E_ARG, "u and out must be non-NULL");
+  if (dtype != STENCIL_F32 && dtype != STENCIL_F64)
+    return fail(STENCIL_E_ARG, "dtype must be STENCIL_F32 or STENCIL_F64");
+  if (n < 0) return fail(STENCIL_E_ARG, "n must be >= 0");
+  if (n == 0) {
+    out[0] = out[1] = out[2] = 0.0;
+    return STENCIL_OK;
+  }
+  const int nblocks = 512;
+  double *buf = nullptr;
+  STENCIL_HIP_TRY(hipMalloc(&buf, sizeof(double) * (nblocks * 5 + 3)));
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_residual(u, ref, dtype, n, buf, nblocks, buf + nblocks * 5, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, buf + nblocks * 5, sizeof(double) * 3,
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return hip_fail(e, "stencil_residual");
+  return STENCIL_OK;
+}
+
+void stencil_plan_destroy(stencil_plan p) {
+  if (!p) return;
+  int cur = 0;
+  bool have = hipGetDevice(&cur) == hipSuccess;
+  for (auto &kv : p->dev) {
+    if (hipSetDevice(kv.first) == hipSuccess) free_device_state(kv.second);
+  }
+  if (have) (void)hipSetDevice(cur);
+  delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+// Temporal computation folding: the m-step operator's weights.
+//
+// Folding m steps merges the repeated terms of the m-step expansion of a
+// point and reassigns their weights (Section 3.1; the folding matrix of
+// Section 3.3, Eq. 4-6).  For a constant-coefficient stencil the reassigned
+// weights are exactly the m-fold self-convolution W_m = w * w * ... * w:
+// applying w twice gives sum_a w[a] sum_b w[b] u[x+a+b] =
+// sum_o (sum_{a+b=o} w[a] w[b]) u[x+o].  W_m is formed here in FP64 on the
+// GPU by m-1 convolutions with w; the FP32 and BF16 forms are derived on the
+// host from it.
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <set>
+
+#include "internal.h"
+
+namespace stencil {
+
+int side_of(int R) { return 2 * R + 1; }
+
+int64_t count_of(int dim, int R) {
+  int64_t s = side_of(R), c = 1;
+  for (int i = 0; i < dim; ++i) c *= s;
+  return c;
+}
+
+int mask_for(int shape, int m) {
+  if (shape == STENCIL_BOX) return MASK_BOX;
+  return m == 1 ? MASK_AXES : MASK_DIAMOND;
+}
+
+// out[o] = sum_b w[b] * a[o - b], o in [-(Ra+r), Ra+r]^d, b in [-r, r]^d in
+// row-major order, one FMA per term that lands inside a's support.
+__global__ void k_fold_conv(const double *__restrict__ a, int Ra,
+                            const double *__restrict__ w, int r, int dim,
+                            double *__restrict__ out) {
+  const int Ro = Ra + r, so = 2 * Ro + 1, sa = 2 * Ra + 1, sw = 2 * r + 1;
+  int64_t total = 1;
+  for (int i = 0; i < dim; ++i) total *= so;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    int o[3] = {0, 0, 0};
+    int64_t q = p;
+    for (int i = dim - 1; i >= 0; --i) {
+      o[i] = (int)(q % so) - Ro;
+      q /= so;
+    }
+    double acc = 0.0;
+    int64_t nb = 1;
+    for (int i = 0; i < dim; ++i) nb *= sw;
+    for (int64_t bi = 0; bi < nb; ++bi) {
+      int b[3] = {0, 0, 0};
+      int64_t t = bi;
+      for (int i = dim - 1; i >= 0; --i) {
+        b[i] = (int)(t % sw) - r;
+        t /= sw;
+      }
+      bool inside = true;
+      int64_t ai = 0;
+      for (int i = 0; i < dim; ++i) {
+        int d = o[i] - b[i];
+        if (d < -Ra || d > Ra) inside = false;
+        ai = ai * sa + (d + Ra);
+      }
+      if (inside) acc = fma(w[bi], a[ai], acc);
+    }
+    out[p] = acc;
+  }
+}
+
+hipError_t launch_fold_conv(const double *a, int Ra, const double *w, int r,
+                            int dim, double *out, hipStream_t s) {
+  int64_t total = count_of(dim, Ra + r);
+  int threads = 256;
+  int blocks = (int)std::min<int64_t>((total + threads - 1) / threads, 1024);
+  hipLaunchKernelGGL(k_fold_conv, dim3(blocks), dim3(threads), 0, s, a, Ra, w,
+                     r, dim, out);
+  return hipGetLastError();
+}
+
+int fold_on_device(const std::vector<double> &w, int dim, int r, int m,
+                   std::vector<double> &Wm) {
+  if (m == 1) {
+    Wm = w;
+    return STENCIL_OK;
+  }
+  const int64_t nmax = count_of(dim, m * r);
+  double *d_w = nullptr, *d_a = nullptr, *d_b = nullptr;
+  hipError_t e = hipMalloc(&d_w, sizeof(double) * w.size());
+  if (e == hipSuccess) e = hipMalloc(&d_a, sizeof(double) * nmax);
+  if (e == hipSuccess) e = hipMalloc(&d_b, sizeof(double) * nmax);
+  if (e == hipSuccess)
+    e = hipMemcpy(d_w, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(d_a, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice);
+  for (int k = 1; k < m && e == hipSuccess; ++k) {
+    e = launch_fold_conv(d_a, k * r, d_w, r, dim, d_b, nullptr);
+    std::swap(d_a, d_b);
+  }
+  if (e == hipSuccess) {
+    Wm.assign(nmax, 0.0);
+    e = hipMemcpy(Wm.data(), d_a, sizeof(double) * nmax, hipMemcpyDeviceToHost);
+  }
+  if (d_w) (void)hipFree(d_w);
+  if (d_a) (void)hipFree(d_a);
+  if (d_b) (void)hipFree(d_b);
+  if (e != hipSuccess) return hip_fail(e, "fold_on_device");
+  return STENCIL_OK;
+}
+
+// FP32 weights of the folded operator: nearest-even rounding of each FP64
+// weight; for m >= 2 the centre weight is reset to
+// fl32((sum w)^m - sum_{o != centre} fl32(W_m[o])) (both sums sequential in
+// row-major order, the power by repeated multiplication), so the FP32
+// operator keeps the folded operator's total weight and the mean of the
+// field does not drift over many folded sweeps.  A centre that rounds to
+// zero is kept as is.
+void round_fold_f32(const std::vector<double> &w, const std::vector<double> &Wm,
+                    int dim, int R, int m, std::vector<float> &out) {
+  out.resize(Wm.size());
+  for (size_t i = 0; i < Wm.size(); ++i) out[i] = (float)Wm[i];
+  if (m < 2) return;
+  const int64_t side = side_of(R);
+  int64_t c = 0;
+  for (int i = 0; i < dim; ++i) c = c * side + R;
+  if (out[c] == 0.0f) return;
+  double s1 = 0.0;
+  for (double v : w) s1 += v;
+  double target = 1.0;
+  for (int k = 0; k < m; ++k) target *= s1;
+  double rest = 0.0;
+  for (int64_t i = 0; i < (int64_t)out.size(); ++i)
+    if (i != c) rest += (double)out[i];
+  out[c] = (float)(target - rest);
+}
+
+uint16_t bf16_rne(float x) {
+  uint32_t b;
+  std::memcpy(&b, &x, 4);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+
+// Scalar profitability analysis (Section 3.2, Eq. 1-3) by enumerating the
+// support S of the stencil and its sum sets S^(+j).
+void profitability(const std::vector<double> &w, int dim, int r, int m,
+                   int64_t *naive, int64_t *folded) {
+  using P = std::array<int, 3>;
+  std::set<P> S;
+  const int s = 2 * r + 1;
+  for (int64_t i = 0; i < (int64_t)w.size(); ++i) {
+    if (w[i] == 0.0) continue;
+    P p{0, 0, 0};
+    int64_t t = i;
+    for (int a = dim - 1; a >= 0; --a) {
+      p[a] = (int)(t % s) - r;
+      t /= s;
+    }
+    S.insert(p);
+  }
+  std::set<P> level{P{0, 0, 0}};
+  int64_t nv = 0;
+  for (int k = 0; k < m; ++k) {
+    nv += (int64_t)S.size() * (int64_t)level.size();
+    std::set<P> next;
+    for (const P &a : level)
+      for (const P &b : S) next.insert(P{a[0] + b[0], a[1] + b[1], a[2] + b[2]});
+    level.swap(next);
+  }
+  if (naive) *naive = nv;
+  if (folded) *folded = (int64_t)level.size();
+}
+
+}  // namespace stencil

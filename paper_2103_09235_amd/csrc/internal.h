@@ -1,0 +1,124 @@
+// Internal declarations shared by the library's translation units.
+// Not part of the public ABI (that is include/stencil.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "stencil.h"
+
+namespace stencil {
+
+// ----------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define STENCIL_HIP_TRY(expr)                                \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) return ::stencil::hip_fail(_e, #expr); \
+  } while (0)
+
+// Mask of possibly nonzero taps of an operator of radius R.
+enum Mask : int {
+  MASK_BOX = 0,     // all (2R+1)^d taps
+  MASK_DIAMOND = 1, // |ox| + |oy| + |oz| <= R (folded star stencils)
+  MASK_AXES = 2     // at most one nonzero offset coordinate (plain stars)
+};
+
+// Geometry of one grid: (nz, ny, nx) with unit leading axes for dim < 3.
+struct Geom {
+  int dim = 0;
+  int64_t nz = 1, ny = 1, nx = 1;
+  int64_t count() const { return nz * ny * nx; }
+};
+
+// One operator as the kernels consume it: weights in the grid's precision,
+// dense (2R+1)^dim row-major, plus its tap list and mask.
+struct OperatorDev {
+  int R = 0;
+  int mask = MASK_BOX;
+  int ntaps = 0;             // nonzero taps
+  void *w_dev = nullptr;     // dense weights on the device (T = float/double)
+  void *taps_dev = nullptr;  // int4 {oz, oy, ox, widx} per nonzero tap
+  std::vector<float> w32;    // host copies for by-value kernel arguments
+  std::vector<double> w64;
+};
+
+// Per-device state owned by a plan.
+struct DeviceState {
+  OperatorDev plain32, plain64, fold32, fold64;
+  bool ready32 = false, ready64 = false;
+  int ready_m = 0;
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  std::map<std::string, hipGraphExec_t> graphs;
+  std::map<std::string, hipGraph_t> graph_src;
+};
+
+}  // namespace stencil
+
+struct stencil_plan_s {
+  int dim = 0, r = 0, shape = 0, boundary = 0, mode = STENCIL_MODE_VECTOR;
+  std::vector<double> w;      // plain weights, FP64, (2r+1)^dim
+  int m = 1;                  // fold depth
+  std::vector<double> Wm;     // folded FP64 weights, (2mr+1)^dim
+  std::vector<float> Wm32;    // folded FP32 weights (rounded, compensated)
+  std::vector<uint16_t> Wm_hi, Wm_lo;  // bf16 split of Wm32
+  std::map<int, stencil::DeviceState> dev;
+};
+
+namespace stencil {
+
+int side_of(int R);
+int64_t count_of(int dim, int R);
+int mask_for(int shape, int m);
+
+// ---------------------------------------------------------------- folding
+int fold_on_device(const std::vector<double> &w, int dim, int r, int m,
+                   std::vector<double> &Wm);
+void round_fold_f32(const std::vector<double> &w, const std::vector<double> &Wm,
+                    int dim, int R, int m, std::vector<float> &out);
+uint16_t bf16_rne(float x);
+void profitability(const std::vector<double> &w, int dim, int r, int m,
+                   int64_t *naive, int64_t *folded);
+
+// ---------------------------------------------------------------- kernels
+struct SweepLaunch {
+  const void *in = nullptr;
+  void *out = nullptr;
+  Geom g;
+  int dtype = STENCIL_F32;
+  const OperatorDev *op = nullptr;
+  int steps = 1;       // operator applications fused into this launch
+  hipStream_t stream = nullptr;
+};
+
+// Generic kernel: one thread per point, any dim / radius, canonical order.
+hipError_t launch_naive(const SweepLaunch &L);
+// Device copy of n elements of esize bytes (a kernel, graph-capture safe).
+hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
+// Tiled kernels; return hipErrorNotSupported if the case is not covered.
+hipError_t launch_sweep1d(const SweepLaunch &L);
+hipError_t launch_sweep2d(const SweepLaunch &L);
+hipError_t launch_sweep3d(const SweepLaunch &L);
+// Largest number of fused steps the 1D kernel takes per launch.
+int sweep1d_max_steps(const SweepLaunch &L);
+
+// FP64 fold convolution: out = a (radius Ra) * w (radius r), dim d.
+hipError_t launch_fold_conv(const double *a, int Ra, const double *w, int r,
+                            int dim, double *out, hipStream_t s);
+
+// Residual reductions.
+hipError_t launch_residual(const void *u, const void *ref, int dtype, int64_t n,
+                           double *partials, int nblocks, double *result,
+                           hipStream_t s);
+
+}  // namespace stencil

@@ -1,0 +1,152 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol include/stencil.h declares, and rejects bad arguments
+synchronously with the documented status codes."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stencil.h")
+
+sf = pytest.importorskip("paper_2103_09235_amd")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stencil_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_and_exports_agree():
+    decl = declared_symbols()
+    assert decl, "no declarations parsed"
+    assert sorted(sf.EXPORTS) == decl
+    lib = ctypes.CDLL(sf.LIB_PATH)
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_last_error():
+    assert "gfx950" in sf.stencil_version()
+    assert isinstance(sf.stencil_last_error(), str)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 1, sf.STENCIL_BOX), sf.STENCIL_E_ARG),
+    ((4, 1, sf.STENCIL_BOX), sf.STENCIL_E_ARG),
+    ((2, 0, sf.STENCIL_BOX), sf.STENCIL_E_ARG),
+    ((2, 1, 7), sf.STENCIL_E_ARG),
+])
+def test_plan_create_rejects(args, code):
+    dim, r, shape = args
+    n = (2 * max(r, 1) + 1) ** max(min(dim, 3), 1)
+    w = np.ones(n)
+    out = ctypes.c_void_p()
+    rc = sf.lib.stencil_plan_create(dim, r, shape, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    0, ctypes.byref(out))
+    assert rc == code
+    assert out.value is None
+    assert sf.stencil_last_error()
+
+
+def test_plan_create_rejects_nonfinite_and_off_axis_star():
+    w = np.ones((3, 3))
+    with pytest.raises(sf.StencilError) as e:
+        sf.stencil_plan_create(2, 1, sf.STENCIL_STAR, w)
+    assert e.value.code == sf.STENCIL_E_ARG
+    w = synth.star2d_weights(0.6, 0.1)
+    w[1, 1] = np.nan
+    with pytest.raises(sf.StencilError) as e:
+        sf.stencil_plan_create(2, 1, sf.STENCIL_STAR, w)
+    assert e.value.code == sf.STENCIL_E_ARG
+    with pytest.raises(sf.StencilError) as e:
+        sf.stencil_plan_create(2, 1, sf.STENCIL_STAR, synth.star2d_weights(0.6, 0.1),
+                               sf.STENCIL_DIRICHLET)
+    assert e.value.code == sf.STENCIL_E_UNSUPPORTED
+    rc = sf.lib.stencil_plan_create(2, 1, 0, None, 0, ctypes.byref(ctypes.c_void_p()))
+    assert rc == sf.STENCIL_E_ARG
+
+
+def test_plan_info_mode_and_profitability():
+    p = sf.Plan(np.ones((3, 3)), sf.STENCIL_BOX)
+    assert p.info() == {"dim": 2, "radius": 1, "m": 1, "folded_radius": 1, "mode": 0}
+    # Section 3.2: 90 naive collect entries, 25 folded, for the 9-point box, m = 2
+    assert p.profitability(2) == (90, 25)
+    star = sf.Plan(synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR)
+    assert star.profitability(2) == (30, 13)
+    assert star.profitability(4) == (220, 41)
+    p.set_mode(sf.STENCIL_MODE_MFMA_BF16X3)
+    assert p.info()["mode"] == sf.STENCIL_MODE_MFMA_BF16X3
+    with pytest.raises(sf.StencilError):
+        p.set_mode(9)
+    p3 = sf.Plan(np.ones((3, 3, 3)), sf.STENCIL_BOX)
+    with pytest.raises(sf.StencilError) as e:
+        p3.set_mode(sf.STENCIL_MODE_MFMA_BF16X3)
+    assert e.value.code == sf.STENCIL_E_UNSUPPORTED
+    with pytest.raises(sf.StencilError):
+        p.profitability(0)
+
+
+def test_plan_f32_weights_start_unfolded():
+    w = synth.WORKLOADS["box2d"].weights
+    p = sf.Plan(w, sf.STENCIL_BOX)
+    assert np.array_equal(p.weights_f32(), w.astype(np.float32))
+
+
+def test_run_validation_before_device_work():
+    p = sf.Plan(synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR)
+    g = sf.stencil_grid()
+    g.data = None
+    g.dtype = sf.STENCIL_F32
+    g.dim = 2
+    g.shape[0] = g.shape[1] = 16
+    assert sf.lib.stencil_run(p.handle, ctypes.byref(g), 5) == sf.STENCIL_E_ARG
+    g.data = 4096
+    assert sf.lib.stencil_run(p.handle, ctypes.byref(g), -1) == sf.STENCIL_E_ARG
+    g.dim = 3
+    assert sf.lib.stencil_run(p.handle, ctypes.byref(g), 5) == sf.STENCIL_E_ARG
+    g.dim = 2
+    g.dtype = 5
+    assert sf.lib.stencil_run(p.handle, ctypes.byref(g), 5) == sf.STENCIL_E_ARG
+    g.dtype = sf.STENCIL_F32
+    g.shape[1] = 2  # below 2*m*r + 1 = 3
+    assert sf.lib.stencil_run(p.handle, ctypes.byref(g), 5) == sf.STENCIL_E_UNSUPPORTED
+    g.shape[1] = 16
+    g.scratch = 4096 + 64  # overlaps data
+    assert sf.lib.stencil_run(p.handle, ctypes.byref(g), 5) == sf.STENCIL_E_ARG
+    g.scratch = None
+    assert sf.lib.stencil_run(p.handle, ctypes.byref(g), 0) == sf.STENCIL_OK
+    assert sf.lib.stencil_run(None, ctypes.byref(g), 1) == sf.STENCIL_E_ARG
+    p.set_mode(sf.STENCIL_MODE_MFMA_BF16X3)
+    g.dtype = sf.STENCIL_F64
+    assert sf.lib.stencil_run(p.handle, ctypes.byref(g), 1) == sf.STENCIL_E_UNSUPPORTED
+
+
+def test_residual_and_fold_validation():
+    out = (ctypes.c_double * 3)()
+    assert sf.lib.stencil_residual(None, None, 0, 10, None, out) == sf.STENCIL_E_ARG
+    assert sf.lib.stencil_residual(4096, None, 7, 10, None, out) == sf.STENCIL_E_ARG
+    assert sf.lib.stencil_residual(4096, None, 0, -1, None, out) == sf.STENCIL_E_ARG
+    assert sf.lib.stencil_residual(4096, None, 0, 0, None, out) == sf.STENCIL_OK
+    p = sf.Plan(np.ones((3, 3)), sf.STENCIL_BOX)
+    assert sf.lib.stencil_fold_weights(p.handle, 0, None, None) == sf.STENCIL_E_ARG
+    assert sf.lib.stencil_fold_weights(p.handle, 65, None, None) == sf.STENCIL_E_UNSUPPORTED
+
+
+def test_batched_validation():
+    assert sf.lib.stencil_run_batched(None, None, 0, 1, None) in (sf.STENCIL_OK, sf.STENCIL_E_ARG)
+    p = sf.Plan(np.ones((3, 3)), sf.STENCIL_BOX)
+    parr = (ctypes.c_void_p * 1)(p.handle.value)
+    g = (sf.stencil_grid * 1)()
+    g[0].dim = 2
+    g[0].dtype = sf.STENCIL_F32
+    g[0].shape[0] = g[0].shape[1] = 64
+    g[0].data = None
+    assert sf.lib.stencil_run_batched(parr, g, 1, 1, None) == sf.STENCIL_E_ARG
+    assert sf.lib.stencil_run_batched(parr, g, 1, -1, None) == sf.STENCIL_E_ARG

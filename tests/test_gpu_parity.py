@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bar: kernels that keep the canonical operation order (every vector-mode and
+exact-order kernel) are bit-exact against the oracle's FP32 mirror (and the
+FP64 oracle itself for FP64 grids); every FP32 result is within 1e-5 (norm-
+wise relative, infinity norm) of the FP64 oracle fed the FP32 weights.
+Sizes span several tiles plus ragged tails; edge cases cover the smallest
+legal sides (2*m*r+1), odd sweep counts and T = 0.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2103_09235_amd as sf  # noqa: E402
+
+DEV = torch.device("cuda:0")
+MODES = {"vector": sf.STENCIL_MODE_VECTOR, "exact": sf.STENCIL_MODE_EXACT_ORDER}
+
+
+def run_gpu(w, shape_kind, u0, T, m=1, mode=sf.STENCIL_MODE_VECTOR, scratch=False):
+    plan = sf.Plan(w, shape_kind)
+    if m > 1:
+        plan.fold(m)
+    plan.set_mode(mode)
+    data = torch.from_numpy(np.ascontiguousarray(u0)).to(DEV)
+    scr = torch.empty_like(data) if scratch else None
+    plan.run(data, T, scr)
+    torch.cuda.synchronize()
+    out = data.cpu().numpy()
+    plan.close()
+    return out
+
+
+CASES_2D = [
+    # (name, weights, kind, shape, T, m)
+    ("star2d", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (300, 517), 9, 1),
+    ("star2d_m2", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (300, 517), 9, 2),
+    ("star2d_m4", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (257, 1031), 12, 4),
+    ("box2d", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (190, 700), 7, 1),
+    ("box2d_m4", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (190, 700), 8, 4),
+    ("box2d_m8", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (140, 530), 16, 8),
+    ("box2d_small_m3", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (7, 7), 7, 3),
+    ("star2d_min_m4", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (9, 9), 9, 4),
+    ("star2d_aligned", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (256, 512), 5, 1),
+    ("box2d_aligned_m2", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (128, 1024), 6, 2),
+]
+
+CASES_3D = [
+    ("star3d", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (20, 33, 70), 5, 1),
+    ("star3d_m2", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (20, 33, 70), 6, 2),
+    ("box3d", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (19, 40, 64), 4, 1),
+    ("box3d_m2", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (17, 36, 128), 5, 2),
+    ("box3d_min_m2", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (5, 5, 5), 4, 2),
+]
+
+CASES_1D = [
+    ("heat1d", synth.heat1d_weights(), sf.STENCIL_STAR, (100_003,), 37, 1),
+    ("heat1d_m3", synth.heat1d_weights(), sf.STENCIL_STAR, (4099,), 10, 3),
+    ("box1d_r2", synth.random_positive_weights(1, 2), sf.STENCIL_BOX, (5000,), 13, 1),
+    ("heat1d_min", synth.heat1d_weights(), sf.STENCIL_STAR, (3,), 5, 1),
+]
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("case", CASES_1D + CASES_2D + CASES_3D, ids=lambda c: c[0])
+def test_f32_bit_exact_vs_mirror(case, mode):
+    name, w, kind, shape, T, m = case
+    w = synth.to_f32_exact(w)
+    u0 = synth.grid_f32(shape)
+    print("case", name, mode, shape, "T", T, "m", m, flush=True)
+    got = run_gpu(w, kind, u0, T, m, MODES[mode])
+    ref = oracle.folded_reference_f32(w, u0, T, m)
+    bad = np.count_nonzero(got != ref)
+    assert bad == 0, "%d of %d elements differ" % (bad, got.size)
+    ref64 = oracle.sweep(w, u0.astype(np.float64), T)
+    assert oracle.errors(got, ref64)["e_rel"] < 1e-5
+
+
+@pytest.mark.parametrize("case", [CASES_1D[0], CASES_1D[2], CASES_2D[1], CASES_3D[3]],
+                         ids=lambda c: c[0])
+def test_f64_vs_oracle(case):
+    name, w, kind, shape, T, m = case
+    u0 = synth.grid_f64(shape)
+    got = run_gpu(w, kind, u0, T, m)
+    if m == 1:
+        ref = oracle.sweep(w, u0, T)
+        assert np.array_equal(got, ref)
+    else:
+        q, s = oracle.schedule(T, m)
+        ref = oracle.sweep(w, oracle.sweep(oracle.fold_weights(w, m), u0, q), s)
+        ref_plain = oracle.sweep(w, u0, T)
+        assert oracle.errors(got, ref)["e_rel"] < 1e-14
+        assert oracle.errors(got, ref_plain)["e_rel"] < 1e-13
+
+
+@pytest.mark.parametrize("name,m", [("star2d", 2), ("star2d", 4), ("box2d", 4), ("box2d", 8),
+                                    ("star3d", 2), ("box3d", 2), ("heat1d", 6)])
+def test_fold_weights_match_oracle(name, m):
+    w = synth.WORKLOADS[name].weights
+    kind = synth.WORKLOADS[name].shape_kind
+    plan = sf.Plan(w, kind)
+    W = plan.fold(m)
+    ref = oracle.fold_weights(w, m)
+    assert np.max(np.abs(W - ref)) <= 1e-16 * max(1.0, np.abs(ref).max()) * 8
+    assert np.array_equal(plan.weights_f32(), oracle.fold_weights_f32(w, m))
+    plan.close()
+
+
+def test_fold_weights_integer_exact():
+    plan = sf.Plan(np.ones((3, 3)), sf.STENCIL_BOX)
+    assert np.array_equal(plan.fold(2), oracle.fold_weights(np.ones((3, 3)), 2))
+    assert np.array_equal(plan.fold(5), oracle.fold_weights(np.ones((3, 3)), 5))
+    plan.close()
+
+
+def test_zero_steps_and_odd_sweeps_and_caller_scratch():
+    w = synth.WORKLOADS["star2d"].weights
+    u0 = synth.grid_f32((64, 96))
+    assert np.array_equal(run_gpu(w, sf.STENCIL_STAR, u0, 0), u0)
+    for T, m in [(1, 1), (3, 1), (5, 2), (7, 4)]:
+        got = run_gpu(w, sf.STENCIL_STAR, u0, T, m, scratch=True)
+        assert np.array_equal(got, oracle.folded_reference_f32(w, u0, T, m)), (T, m)
+
+
+def test_split_runs_compose():
+    """run(T1) then run(T2) equals run(T1 + T2) bit for bit when m divides T1."""
+    w = synth.WORKLOADS["box2d"].weights
+    u0 = synth.grid_f32((150, 333))
+    plan = sf.Plan(w, sf.STENCIL_BOX)
+    plan.fold(4)
+    a = torch.from_numpy(u0).to(DEV)
+    b = a.clone()
+    plan.run(a, 8)
+    plan.run(a, 6)
+    plan.run(b, 14)
+    torch.cuda.synchronize()
+    # 14 = 3 folded + 2 plain; 8 + 6 = (2 folded) + (1 folded + 2 plain)
+    assert torch.equal(a, b)
+    plan.close()
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_translation_equivariance_bitwise(dim):
+    shape = {1: (8191,), 2: (131, 257), 3: (24, 40, 72)}[dim]
+    w = synth.to_f32_exact(synth.random_positive_weights(dim, 1))
+    u0 = synth.grid_f32(shape)
+    shift = {1: (77,), 2: (5, 131), 3: (3, 9, 33)}[dim]
+    axes = tuple(range(dim))
+    a = run_gpu(w, sf.STENCIL_BOX, np.roll(u0, shift, axes), 6, 2)
+    b = np.roll(run_gpu(w, sf.STENCIL_BOX, u0, 6, 2), shift, axes)
+    assert np.array_equal(a, b)
+
+
+def test_residual_sums():
+    u = synth.grid_f32((1000, 777))
+    v = synth.grid_f32((1000, 777), stream=9)
+    tu = torch.from_numpy(u).to(DEV)
+    tv = torch.from_numpy(v).to(DEV)
+    s, d, mx = sf.stencil_residual(tu, tv)
+    assert abs(s - oracle.exact_sum(u)) <= 4 * 2.0 ** -53 * abs(s)
+    diff = np.abs(u.astype(np.float64) - v.astype(np.float64))
+    assert abs(d - oracle.exact_sum(diff)) <= 4 * 2.0 ** -53 * d
+    assert mx == diff.max()
+    u64 = synth.grid_f64((3, 5, 7))
+    s2, _, _ = sf.stencil_residual(torch.from_numpy(u64).to(DEV))
+    assert abs(s2 - oracle.exact_sum(u64)) <= 2 * 2.0 ** -53 * abs(s2)
+
+
+def test_errors_surface_from_run():
+    plan = sf.Plan(synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR)
+    plan.fold(4)
+    t = torch.zeros((8, 64), device=DEV)
+    with pytest.raises(sf.StencilError) as e:
+        plan.run(t, 4)
+    assert e.value.code == sf.STENCIL_E_UNSUPPORTED
+    host = torch.zeros((64, 64))
+    g = sf.stencil_grid()
+    g.data = host.data_ptr()
+    g.dtype = sf.STENCIL_F32
+    g.dim = 2
+    g.shape[0] = g.shape[1] = 64
+    import ctypes
+    assert sf.lib.stencil_run(plan.handle, ctypes.byref(g), 4) == sf.STENCIL_E_ARG
+    plan.close()
