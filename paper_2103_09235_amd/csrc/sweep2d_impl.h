@@ -1,0 +1,238 @@
+// Tiled 2D sweep for gfx950: one wavefront per tile, streaming down y.
+//
+// One application of a (2R+1)^2 operator (the plain stencil of Section 1, or
+// the folded m-step operator of Section 3.3 with R = m*r).  The tile is a
+// column strip of 64*VX points (VX consecutive x per lane, loaded as one
+// 16-byte vector when VX*sizeof(T) = 16) and BY output rows.  Input rows
+// stream through once, top to bottom:
+//  - each row (plus R halo columns each side, periodic wrap) is staged in a
+//    double-buffered LDS row so a lane can read its neighbours' columns;
+//  - the 2R+1 output rows a row contributes to are accumulated in registers
+//    (the accumulator queue); when row j arrives, output row j-R completes
+//    and is stored, and its registers start output row j+R+1.
+// This register reuse along the streaming axis plays the part of the
+// paper's shifts reusing (Section 3.4): each input value is loaded from HBM
+// once per sweep and read from LDS once per lane that needs it.
+//
+// Every output keeps the canonical operation order: acc = +0, then one FMA
+// per tap of the mask in row-major offset order (rows arrive in ascending
+// oy, taps within a row in ascending ox).  Taps inside the mask whose weight
+// is zero leave the accumulator unchanged (fma(0, u, acc) == acc for finite
+// u and acc != -0), so results are bit-identical to a loop that skips them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace stencil {
+namespace k2d {
+
+template <typename T, int N>
+struct WArr {
+  T v[N];
+};
+
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <int MASK, int R>
+__host__ __device__ constexpr bool in_mask(int oy, int ox) {
+  return MASK == MASK_BOX ? true
+         : MASK == MASK_DIAMOND ? ((oy < 0 ? -oy : oy) + (ox < 0 ? -ox : ox) <= R)
+                                : (oy == 0 || ox == 0);
+}
+
+template <typename T, int VX>
+struct Vec {
+  T v[VX];
+};
+
+template <typename T, int VX>
+__device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&d)[VX]) {
+  if constexpr (VX * sizeof(T) == 16) {
+    using V = __attribute__((ext_vector_type(16 / sizeof(T)))) T;
+    V t = *reinterpret_cast<const V *>(p);
+#pragma unroll
+    for (int i = 0; i < VX; ++i) d[i] = t[i];
+  } else if constexpr (VX * sizeof(T) == 8) {
+    using V = __attribute__((ext_vector_type(8 / sizeof(T)))) T;
+    V t = *reinterpret_cast<const V *>(p);
+#pragma unroll
+    for (int i = 0; i < VX; ++i) d[i] = t[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < VX; ++i) d[i] = p[i];
+  }
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ void store_vec(T *__restrict__ p, const T (&s)[VX]) {
+  if constexpr (VX * sizeof(T) == 16) {
+    using V = __attribute__((ext_vector_type(16 / sizeof(T)))) T;
+    V t;
+#pragma unroll
+    for (int i = 0; i < VX; ++i) t[i] = s[i];
+    *reinterpret_cast<V *>(p) = t;
+  } else if constexpr (VX * sizeof(T) == 8) {
+    using V = __attribute__((ext_vector_type(8 / sizeof(T)))) T;
+    V t;
+#pragma unroll
+    for (int i = 0; i < VX; ++i) t[i] = s[i];
+    *reinterpret_cast<V *>(p) = t;
+  } else {
+#pragma unroll
+    for (int i = 0; i < VX; ++i) p[i] = s[i];
+  }
+}
+
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Blocks are dealt round-robin to the 8 XCDs; renumber them so consecutive
+// tiles (which share halo rows and columns) run on the same XCD and L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  if ((nb & 7) != 0) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+template <int MASK, int R>
+__host__ __device__ constexpr int mask_taps() {
+  int n = 0;
+  for (int oy = -R; oy <= R; ++oy)
+    for (int ox = -R; ox <= R; ++ox) n += in_mask<MASK, R>(oy, ox) ? 1 : 0;
+  return n;
+}
+
+// Rotating the accumulator queue by unrolling 2R+1 rows avoids register
+// moves but multiplies the code size; large operators shift instead.
+template <int MASK, int R, int VX>
+__host__ __device__ constexpr bool rotate_queue() {
+  return (2 * R + 1) * mask_taps<MASK, R>() * VX <= 4096;
+}
+
+template <typename T, int R, int MASK, int VX>
+__global__ void __launch_bounds__(64)
+k_sweep2d(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
+          int tiles_y, WArr<T, (2 * R + 1) * (2 * R + 1)> W) {
+  constexpr int S = 2 * R + 1;
+  constexpr int NU = S;
+  constexpr bool ROT = rotate_queue<MASK, R, VX>();
+  constexpr int UNR = ROT ? NU : 1;
+  constexpr int BX = 64 * VX;
+  constexpr int RP = ((R + VX - 1) / VX) * VX;
+  constexpr int LW = BX + 2 * RP;
+  __shared__ T lds[2][LW];
+
+  const int lane = threadIdx.x;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = t / tiles_y, ty = t - tx * tiles_y;
+  const int x0 = tx * BX, y0 = ty * BY;
+  const int w = min(BX, nx - x0);
+  const int y1 = min(y0 + BY, ny);
+  const bool valid = lane * VX < w;
+  const int xl = x0 + lane * VX;
+
+  int hx = -1, hpos = 0;
+  if (lane < R) {
+    hx = wrap1(x0 - R + lane, nx);
+    hpos = RP - R + lane;
+  } else if (lane < 2 * R) {
+    hx = wrap1(x0 + w + lane - R, nx);
+    hpos = RP + w + lane - R;
+  }
+
+  T acc[NU][VX];
+#pragma unroll
+  for (int k = 0; k < NU; ++k)
+#pragma unroll
+    for (int v = 0; v < VX; ++v) acc[k][v] = T(0);
+
+  const int jstart = y0 - R, jend = y1 + R;
+
+  // one-row-ahead prefetch of the centre vector and the halo element
+  T nxt[VX];
+  T nxth = T(0);
+#pragma unroll
+  for (int v = 0; v < VX; ++v) nxt[v] = T(0);
+  {
+    const int jj = wrap1(jstart, ny);
+    const T *row = in + (size_t)jj * nx;
+    if (valid) load_vec<T, VX>(row + xl, nxt);
+    if (hx >= 0) nxth = row[hx];
+  }
+
+  for (int jb = jstart; jb < jend; jb += UNR) {
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int j = jb + u;
+      if (j < jend) {
+        T cur[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) cur[v] = nxt[v];
+        const T curh = nxth;
+        if (j + 1 < jend) {
+          const int jj = wrap1(j + 1, ny);
+          const T *row = in + (size_t)jj * nx;
+          if (valid) load_vec<T, VX>(row + xl, nxt);
+          if (hx >= 0) nxth = row[hx];
+        }
+        T *L = lds[(j - jstart) & 1];
+        if (valid) store_vec<T, VX>(L + RP + lane * VX, cur);
+        if (hx >= 0) L[hpos] = curh;
+        __syncthreads();
+        // window: win[i] = value at x = xl + i - RP, i in [RP-R, RP+VX+R)
+        T win[VX + 2 * RP];
+#pragma unroll
+        for (int i = 0; i < RP; ++i) {
+          if (i >= RP - R) win[i] = L[lane * VX + i];
+          else win[i] = T(0);
+        }
+#pragma unroll
+        for (int v = 0; v < VX; ++v) win[RP + v] = cur[v];
+#pragma unroll
+        for (int i = RP + VX; i < VX + 2 * RP; ++i) {
+          if (i < RP + VX + R) win[i] = L[lane * VX + i];
+          else win[i] = T(0);
+        }
+#pragma unroll
+        for (int k = S - 1; k >= 0; --k) {
+          // pending output row y = j - R + k receives weight row oy = R - k
+          const int y = j - R + k;
+          if (y >= y0 && y < y1) {
+            const int slot = ROT ? (u + k) % NU : k;
+            const int oy = R - k;
+#pragma unroll
+            for (int ox = -R; ox <= R; ++ox) {
+              if (in_mask<MASK, R>(oy, ox)) {
+                const T wt = W.v[(oy + R) * S + (ox + R)];
+#pragma unroll
+                for (int v = 0; v < VX; ++v)
+                  acc[slot][v] = fmat(wt, win[RP + v + ox], acc[slot][v]);
+              }
+            }
+          }
+        }
+        // output row j - R is complete
+        const int yd = j - R;
+        if constexpr (ROT) {
+          if (yd >= y0) {
+            if (valid) store_vec<T, VX>(out + (size_t)yd * nx + xl, acc[u % NU]);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) acc[u % NU][v] = T(0);
+          }
+        } else {
+          if (yd >= y0 && valid) store_vec<T, VX>(out + (size_t)yd * nx + xl, acc[0]);
+#pragma unroll
+          for (int k = 0; k + 1 < NU; ++k)
+#pragma unroll
+            for (int v = 0; v < VX; ++v) acc[k][v] = acc[k + 1][v];
+#pragma unroll
+          for (int v = 0; v < VX; ++v) acc[NU - 1][v] = T(0);
+        }
+      }
+    }
+  }
+}
+
+}  // namespace k2d
+}  // namespace stencil

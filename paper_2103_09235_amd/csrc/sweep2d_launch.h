@@ -1,0 +1,56 @@
+// Host-side launch of one instantiation of the tiled 2D sweep.  Each
+// radius is instantiated in its own translation unit (sweep2d_r*.hip) so the
+// library builds in parallel.
+#pragma once
+
+#include <cstdlib>
+
+#include "sweep2d_impl.h"
+
+namespace stencil {
+namespace k2d {
+
+template <typename T, int R, int MASK, int VX>
+hipError_t launch_one(const SweepLaunch &L, const std::vector<T> &w) {
+  constexpr int S = 2 * R + 1;
+  constexpr int BX = 64 * VX;
+  WArr<T, S * S> W;
+  for (int i = 0; i < S * S; ++i) W.v[i] = w[i];
+  const int ny = (int)L.g.ny, nx = (int)L.g.nx;
+  const int tiles_x = (nx + BX - 1) / BX;
+  int by = 0;
+  if (const char *e = std::getenv("STENCIL_TILE_Y")) by = std::atoi(e);
+  if (by <= 0) {
+    const int target_tiles_y = (4096 + tiles_x - 1) / tiles_x;
+    by = (ny + target_tiles_y - 1) / target_tiles_y;
+  }
+  by = std::max(by, std::max(8, 4 * R));
+  by = std::min(by, ny);
+  const int tiles_y = (ny + by - 1) / by;
+  const int64_t blocks = (int64_t)tiles_x * tiles_y;
+  if (blocks > (1LL << 31) - 1) return hipErrorNotSupported;
+  hipLaunchKernelGGL((k_sweep2d<T, R, MASK, VX>), dim3((unsigned)blocks), dim3(64), 0,
+                     L.stream, (const T *)L.in, (T *)L.out, ny, nx, by, tiles_y, W);
+  return hipGetLastError();
+}
+
+template <typename T, int R, int MASK>
+hipError_t launch_vx(const SweepLaunch &L, const std::vector<T> &w) {
+  constexpr int VXW = 16 / sizeof(T);
+  const bool aligned = ((uintptr_t)L.in % 16 == 0) && ((uintptr_t)L.out % 16 == 0) &&
+                       (L.g.nx % VXW == 0);
+  if (aligned) return launch_one<T, R, MASK, VXW>(L, w);
+  return launch_one<T, R, MASK, 1>(L, w);
+}
+
+template <typename T, int R>
+hipError_t launch_r(const SweepLaunch &L) {
+  const std::vector<T> *w;
+  if constexpr (sizeof(T) == 4) w = &L.op->w32;
+  else w = &L.op->w64;
+  if (L.op->mask == MASK_BOX) return launch_vx<T, R, MASK_BOX>(L, *w);
+  return launch_vx<T, R, MASK_DIAMOND>(L, *w);  // the diamond contains the axes
+}
+
+}  // namespace k2d
+}  // namespace stencil

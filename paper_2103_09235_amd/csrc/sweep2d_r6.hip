@@ -1,0 +1,8 @@
+// Tiled 2D sweep, radius 6 (see sweep2d_impl.h).
+#include "sweep2d_launch.h"
+namespace stencil {
+namespace k2d {
+template hipError_t launch_r<float, 6>(const SweepLaunch &);
+
+}  // namespace k2d
+}  // namespace stencil
