@@ -1,0 +1,296 @@
+#!/usr/bin/env python3
+"""Benchmark: iterated stencil sweeps with temporal computation folding on one
+MI355X, reported as GStencil/s (grid points x original time steps per second)
+and as a fraction of the roofline that bounds the dominant kernel.
+
+Default workload: the 2D 5-point star (centre 0.6, neighbours 0.1, FP32
+weights), 8192 x 8192 FP32 periodic grid, T = 1000 original steps, uniform
+[0, 1) initial values (SplitMix64, seed 2103).  One step = one stencil_run of
+all T steps (plan and folded weights prepared beforehand, grid resident in
+HBM).  The headline form is the fold depth m = 4 (41-point folded operator);
+the plain sweep and m = 2 are timed beside it under "forms".
+
+Other workloads (--workload): heat1d, star3d, box3d, box2d, batched.
+
+Prints ONE JSON line on stdout.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_VECTOR_TFLOPS = 157.3      # MI355X FP32 vector, published
+FP64_VECTOR_TFLOPS = 78.6       # MI355X FP64 vector, published
+BF16_MFMA_TFLOPS = 2500.0       # MI355X dense BF16 matrix, published
+METRIC = "GStencil/s and % HBM roofline, plain vs folded/MFMA/batched at stated error"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="star2d",
+                    choices=["star2d", "heat1d", "star3d", "box3d", "box2d", "batched"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2103_09235_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_key: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, if one
+    exists for this kernel and workload and the kernel sources have not
+    changed since it was taken (its 'source-hash' line)."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (kernel_key, workload))
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source-hash:\s*(\w+)", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    b = re.search(r"hbm-bytes-per-launch:\s*([0-9.eE+]+)", text)
+    return float(b.group(1)) if b else None
+
+
+def time_runs(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def cpu_baseline(w, shape_full, dtype, T_full, budget_s):
+    """The oracle as it stands, timed on a bounded sample of the workload: a
+    smaller grid of the same dimension and distribution, for a number of
+    original steps chosen to fill about budget_s seconds."""
+    import numpy as np
+    import oracle
+    import synth
+    dim = len(shape_full)
+    side = {1: 1 << 18, 2: 1024, 3: 96}[dim]
+    shape = tuple(min(s, side) for s in shape_full)
+    u0 = synth.grid_f64(shape)
+    t0 = time.perf_counter()
+    oracle.sweep(w, u0, 2)
+    per_step = max((time.perf_counter() - t0) / 2, 1e-6)
+    T = int(max(2, min(T_full, budget_s / per_step)))
+    t0 = time.perf_counter()
+    oracle.sweep(w, u0, T)
+    dt = time.perf_counter() - t0
+    n = int(np.prod(shape))
+    return {
+        "value": round(n * T / dt / 1e9, 4),
+        "unit": "GStencil/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": "FP64 naive sweep, grid %s, %d of the %d original steps, %.1f s" % (
+            "x".join(map(str, shape)), T, T_full, dt),
+    }
+
+
+def fp64_reference(sf, w, kind, u0, T):
+    """The same T steps in FP64 by the library's plain FP64 sweep, which the
+    parity tests pin bit-for-bit to the FP64 oracle."""
+    import numpy as np
+    import torch
+    plan = sf.Plan(w, kind)
+    d = torch.from_numpy(np.asarray(u0, dtype=np.float64)).cuda()
+    plan.run(d, T)
+    torch.cuda.synchronize()
+    plan.close()
+    return d
+
+
+def error_vs(ref64, got):
+    import torch
+    d = (got.double() - ref64).abs().max().item()
+    nref = ref64.abs().max().item()
+    mean = ref64.mean().item()
+    ndet = (ref64 - mean).abs().max().item()
+    return d / nref, d / ndet if ndet > 0 else d
+
+
+def bench_grid(args, wl_name):
+    import numpy as np
+    import torch
+    import synth
+    import paper_2103_09235_amd as sf
+
+    wl = synth.WORKLOADS[wl_name]
+    shape, T, w = wl.shape, wl.T, wl.weights
+    f32 = wl.dtype == "f32"
+    esz = 4 if f32 else 8
+    n = int(np.prod(shape))
+    log("[bench] workload %s: %s" % (wl_name, wl.note))
+    u0 = synth.grid_f32(shape) if f32 else synth.grid_f64(shape)
+    dev = torch.device("cuda:0")
+    data = torch.from_numpy(u0).to(dev)
+    scratch = torch.empty_like(data)
+    s0, _, _ = sf.stencil_residual(data)
+
+    forms = {}
+    ref64 = None
+    modes = [("vector", sf.STENCIL_MODE_VECTOR)]
+    headline = None
+    for m in wl.folds:
+        form_modes = list(modes)
+        if wl_name == "box2d" and m > 1 and hasattr(sf, "STENCIL_MODE_MFMA_BF16X3"):
+            form_modes.append(("mfma_bf16x3", sf.STENCIL_MODE_MFMA_BF16X3))
+        for mode_name, mode in form_modes:
+            plan = sf.Plan(w, wl.shape_kind)
+            if m > 1:
+                plan.fold(m)
+            try:
+                plan.set_mode(mode)
+            except sf.StencilError as e:
+                log("[bench] skip m=%d %s: %s" % (m, mode_name, e))
+                continue
+            data.copy_(torch.from_numpy(u0).to(dev))
+
+            def step():
+                plan.run(data, T, scratch)
+
+            log("[bench] m=%d %s: timing %d steps of T=%d" % (m, mode_name, args.steps, T))
+            try:
+                el, wall = time_runs(step, args.steps, args.warmup)
+            except sf.StencilError as e:
+                log("[bench] skip m=%d %s: %s" % (m, mode_name, e))
+                continue
+            q, r = divmod(T, m) if m > 1 else (0, T)
+            sweeps = q + r
+            # mass after the timed runs: data has advanced (warmup+steps)*T steps
+            total_T = (args.warmup + args.steps) * T
+            s1, _, _ = sf.stencil_residual(data)
+            w_eff = w.astype(np.float32).astype(np.float64) if f32 else w
+            expect = math.fsum(float(v) for v in w_eff.ravel()) ** total_T * s0
+            mass_rel = abs(s1 - expect) / abs(expect)
+            # error of one T-step run against the FP64 sweep
+            data.copy_(torch.from_numpy(u0).to(dev))
+            plan.run(data, T, scratch)
+            if ref64 is None:
+                ref64 = fp64_reference(sf, w, wl.shape_kind, u0, T)
+            err, err_detr = error_vs(ref64, data)
+            gst = n * T * args.steps / el / 1e9
+            sweep_ms = el / args.steps / sweeps * 1e3
+            algo_bytes = 2 * esz * n
+            taps = int(np.count_nonzero(plan.fold(m) if m > 1 else w))
+            flops = 2 * taps * n
+            key = "%s_m%d_%s" % (wl_name, m, mode_name)
+            forms[key] = {
+                "m": m, "mode": mode_name, "gstencil_s": round(gst, 2),
+                "ms_per_run": round(el / args.steps * 1e3, 4),
+                "ms_per_sweep": round(sweep_ms, 5),
+                "sweep_launches_per_run": sweeps, "taps": taps,
+                "hbm_gbs_algorithmic": round(algo_bytes / (sweep_ms / 1e3) / 1e9, 1),
+                "hbm_frac": round(algo_bytes / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "e_rel_vs_fp64": err, "e_detrended_vs_fp64": err_detr,
+                "mass_rel_drift": mass_rel, "mass_T": total_T,
+                "wall_s": round(wall, 3),
+            }
+            log("[bench]   %.1f GStencil/s, %.4f ms/sweep, e_rel %.2e (detrended %.2e), "
+                "mass drift %.2e" % (gst, sweep_ms, err, err_detr, mass_rel))
+            if headline is None or gst > headline[1]:
+                headline = (key, gst, el, sweep_ms, algo_bytes, flops, m, mode_name, taps)
+            plan.close()
+    key, gst, el, sweep_ms, algo_bytes, flops, m, mode_name, taps = headline
+    intensity = flops / algo_bytes
+    if mode_name.startswith("mfma"):
+        peak_t = BF16_MFMA_TFLOPS
+    else:
+        peak_t = FP32_VECTOR_TFLOPS if f32 else FP64_VECTOR_TFLOPS
+    ridge = peak_t * 1e12 / (HBM_PEAK_GBS * 1e9)
+    dur = sweep_ms / 1e3
+    if intensity < ridge or mode_name.startswith("mfma"):
+        roof = {"bound": "hbm", "achieved": round(algo_bytes / dur / 1e9, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": round(flops / dur / 1e12, 2),
+                "peak": peak_t, "unit": "TFLOP/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = traffic_from_profiles("sweep%dd_m%d" % (wl.dim, m), wl_name)
+    roof["kernel"] = "k_sweep%dd R=%d (%s, %d taps)" % (wl.dim, m * ((w.shape[0] - 1) // 2),
+                                                        mode_name, taps)
+    roof["launch_ms"] = round(sweep_ms, 5)
+    roof["algorithmic_bytes_per_launch"] = algo_bytes
+    roof["algorithmic_flops_per_launch"] = flops
+    res = {
+        "metric": METRIC,
+        "value": round(gst, 2),
+        "unit": "GStencil/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if f32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.note, "grid": list(shape), "T": T, "fold_m": m,
+                   "mode": mode_name, "points": n},
+        "roofline": roof,
+        "forms": forms,
+    }
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle baseline")
+        res["cpu_baseline"] = cpu_baseline(w, shape, wl.dtype, T, args.cpu_seconds)
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
+              "(a grid would shard by slabs with one halo exchange per folded sweep; "
+              "not built). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.workload == "batched":
+        from bench_batched import bench_batched  # noqa: WPS433
+        res = bench_batched(args)
+    else:
+        res = bench_grid(args, args.workload)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

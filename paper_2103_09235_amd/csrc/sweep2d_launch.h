@@ -10,7 +10,7 @@
 namespace stencil {
 namespace k2d {
 
-template <typename T, int R, int MASK, int VX>
+template <typename T, int R, int MASK, int VX, int PD>
 hipError_t launch_one(const SweepLaunch &L, const std::vector<T> &w) {
   constexpr int S = 2 * R + 1;
   constexpr int BX = 64 * VX;
@@ -29,7 +29,7 @@ hipError_t launch_one(const SweepLaunch &L, const std::vector<T> &w) {
   const int tiles_y = (ny + by - 1) / by;
   const int64_t blocks = (int64_t)tiles_x * tiles_y;
   if (blocks > (1LL << 31) - 1) return hipErrorNotSupported;
-  hipLaunchKernelGGL((k_sweep2d<T, R, MASK, VX>), dim3((unsigned)blocks), dim3(64), 0,
+  hipLaunchKernelGGL((k_sweep2d<T, R, MASK, VX, PD>), dim3((unsigned)blocks), dim3(64), 0,
                      L.stream, (const T *)L.in, (T *)L.out, ny, nx, by, tiles_y, W);
   return hipGetLastError();
 }
@@ -39,8 +39,17 @@ hipError_t launch_vx(const SweepLaunch &L, const std::vector<T> &w) {
   constexpr int VXW = 16 / sizeof(T);
   const bool aligned = ((uintptr_t)L.in % 16 == 0) && ((uintptr_t)L.out % 16 == 0) &&
                        (L.g.nx % VXW == 0);
-  if (aligned) return launch_one<T, R, MASK, VXW>(L, w);
-  return launch_one<T, R, MASK, 1>(L, w);
+  if (!aligned) return launch_one<T, R, MASK, 1, 1>(L, w);
+  if constexpr (R <= 2 && rotate_queue<MASK, R, VXW>()) {
+    // two rows of look-ahead measured best on gfx950 (STENCIL_PD overrides)
+    static const int pd = [] {
+      const char *e = std::getenv("STENCIL_PD");
+      return e ? std::atoi(e) : 2;
+    }();
+    if (pd == 2) return launch_one<T, R, MASK, VXW, 2>(L, w);
+    if (pd == 4) return launch_one<T, R, MASK, VXW, 4>(L, w);
+  }
+  return launch_one<T, R, MASK, VXW, 1>(L, w);
 }
 
 template <typename T, int R>
