@@ -49,6 +49,10 @@ def parse():
                     choices=["star2d", "heat1d", "star3d", "box3d", "box2d", "batched"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--only-m", type=int, default=0,
+                    help="time only this fold depth (profiling runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 256 MiB device copy (PMC byte-counter calibration)")
     return ap.parse_args()
 
 
@@ -102,14 +106,12 @@ def cpu_baseline(w, shape_full, dtype, T_full, budget_s):
     import numpy as np
     import oracle
     import synth
-    dim = len(shape_full)
-    side = {1: 1 << 18, 2: 1024, 3: 96}[dim]
-    shape = tuple(min(s, side) for s in shape_full)
+    shape = tuple(shape_full)
     u0 = synth.grid_f64(shape)
     t0 = time.perf_counter()
-    oracle.sweep(w, u0, 2)
-    per_step = max((time.perf_counter() - t0) / 2, 1e-6)
-    T = int(max(2, min(T_full, budget_s / per_step)))
+    oracle.sweep(w, u0, 1)
+    per_step = max(time.perf_counter() - t0, 1e-6)
+    T = int(max(1, min(T_full, budget_s / per_step)))
     t0 = time.perf_counter()
     oracle.sweep(w, u0, T)
     dt = time.perf_counter() - t0
@@ -169,6 +171,8 @@ def bench_grid(args, wl_name):
     modes = [("vector", sf.STENCIL_MODE_VECTOR)]
     headline = None
     for m in wl.folds:
+        if args.only_m and m != args.only_m:
+            continue
         form_modes = list(modes)
         if wl_name == "box2d" and m > 1 and hasattr(sf, "STENCIL_MODE_MFMA_BF16X3"):
             form_modes.append(("mfma_bf16x3", sf.STENCIL_MODE_MFMA_BF16X3))
@@ -284,6 +288,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        n = 64 << 20
+        x = torch.rand(n, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(4):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"metric": "copy calibration", "bytes_read_per_launch": 4 * n,
+                          "bytes_written_per_launch": 4 * n, "launches": 4}), flush=True)
+        return
     if args.workload == "batched":
         from bench_batched import bench_batched  # noqa: WPS433
         res = bench_batched(args)

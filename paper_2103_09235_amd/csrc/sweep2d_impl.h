@@ -116,7 +116,7 @@ __host__ __device__ constexpr bool rotate_queue() {
 template <typename T, int R, int MASK, int VX, int PD>
 __global__ void __launch_bounds__(64)
 k_sweep2d(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
-          int tiles_y, WArr<T, (2 * R + 1) * (2 * R + 1)> W) {
+          int tiles_y, int tiles_x, int xfast, WArr<T, (2 * R + 1) * (2 * R + 1)> W) {
   constexpr int S = 2 * R + 1;
   constexpr int NU = S;
   constexpr bool ROT = rotate_queue<MASK, R, VX>();
@@ -129,7 +129,10 @@ k_sweep2d(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
 
   const int lane = threadIdx.x;
   const int t = xcd_tile(blockIdx.x, gridDim.x);
-  const int tx = t / tiles_y, ty = t - tx * tiles_y;
+  // xfast: horizontally adjacent tiles are consecutive (they run together
+  // and share halo columns through L2); else vertically adjacent ones are.
+  const int tx = xfast ? t % tiles_x : t / tiles_y;
+  const int ty = xfast ? t / tiles_x : t - tx * tiles_y;
   const int x0 = tx * BX, y0 = ty * BY;
   const int w = min(BX, nx - x0);
   const int y1 = min(y0 + BY, ny);
