@@ -49,6 +49,7 @@ bool on_axes(int64_t idx, int dim, int r) {
 void free_operator(OperatorDev &op) {
   if (op.w_dev) (void)hipFree(op.w_dev);
   if (op.taps_dev) (void)hipFree(op.taps_dev);
+  if (op.mfma_b) (void)hipFree(op.mfma_b);
   op = OperatorDev();
 }
 
@@ -97,6 +98,12 @@ int build_operator(const std::vector<T> &w, int dim, int R, int mask,
                               hipMemcpyHostToDevice));
   if constexpr (sizeof(T) == 4) {
     op.w32.assign(w.begin(), w.end());
+    if (dim == 2 && R <= 8) {
+      const std::vector<uint16_t> t = mfma_b_table(op.w32, R);
+      STENCIL_HIP_TRY(hipMalloc(&op.mfma_b, t.size() * sizeof(uint16_t)));
+      STENCIL_HIP_TRY(hipMemcpy(op.mfma_b, t.data(), t.size() * sizeof(uint16_t),
+                                hipMemcpyHostToDevice));
+    }
   } else {
     op.w64.assign(w.begin(), w.end());
   }
@@ -132,6 +139,7 @@ int ensure_operators(stencil_plan p, int device, int dtype) {
 
 hipError_t dispatch(stencil_plan p, const SweepLaunch &L) {
   if (p->mode == STENCIL_MODE_EXACT_ORDER) return launch_naive(L);
+  if (p->mode == STENCIL_MODE_MFMA_BF16X3) return launch_mfma2d(L);
   hipError_t e = hipErrorNotSupported;
   if (L.g.dim == 1) e = launch_sweep1d(L);
   else if (L.g.dim == 2) e = launch_sweep2d(L);
@@ -306,6 +314,8 @@ int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
   if (!g->data) return fail(STENCIL_E_ARG, "data is NULL");
   if (p->mode == STENCIL_MODE_MFMA_BF16X3 && g->dtype != STENCIL_F32)
     return fail(STENCIL_E_UNSUPPORTED, "MFMA mode takes FP32 grids only");
+  if (p->mode == STENCIL_MODE_MFMA_BF16X3 && p->m * p->r > 8)
+    return fail(STENCIL_E_UNSUPPORTED, "MFMA mode needs a folded radius m*r <= 8");
   Geom geo;
   geo.dim = p->dim;
   int64_t n[3] = {1, 1, 1};

@@ -50,6 +50,7 @@ struct OperatorDev {
   void *taps_dev = nullptr;  // int4 {oz, oy, ox, widx} per nonzero tap
   std::vector<float> w32;    // host copies for by-value kernel arguments
   std::vector<double> w64;
+  void *mfma_b = nullptr;    // BF16 hi/lo B-fragment table (2D FP32, R <= 8)
 };
 
 // Per-device state owned by a plan.
@@ -109,6 +110,10 @@ hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t s)
 hipError_t launch_sweep1d(const SweepLaunch &L);
 hipError_t launch_sweep2d(const SweepLaunch &L);
 hipError_t launch_sweep3d(const SweepLaunch &L);
+// 2D operators of radius <= 8 as BF16x3 matrix-core products (FP32 grids).
+hipError_t launch_mfma2d(const SweepLaunch &L);
+// Host-built B-fragment table the matrix-core kernel loads per lane.
+std::vector<uint16_t> mfma_b_table(const std::vector<float> &w, int R);
 // Largest number of fused steps the 1D kernel takes per launch.
 int sweep1d_max_steps(const SweepLaunch &L);
 

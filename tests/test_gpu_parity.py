@@ -191,3 +191,49 @@ def test_errors_surface_from_run():
     import ctypes
     assert sf.lib.stencil_run(plan.handle, ctypes.byref(g), 4) == sf.STENCIL_E_ARG
     plan.close()
+
+
+# ------------------------------------------------ BF16x3 matrix-core form
+
+MFMA_CASES = [
+    # (name, weights, kind, shape, T, m)
+    ("box2d_m4", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (190, 700), 16, 4),
+    ("box2d_m8", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (140, 530), 24, 8),
+    ("box2d_m8_min", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (17, 17), 16, 8),
+    ("box2d_m4_rem", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (257, 129), 18, 4),
+    ("star2d_m4", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (96, 260), 12, 4),
+    ("box2d_plain", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (64, 64), 5, 1),
+    ("box2d_m2_aligned", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (512, 1024), 8, 2),
+]
+
+
+@pytest.mark.parametrize("case", MFMA_CASES, ids=lambda c: c[0])
+def test_mfma_bf16x3_within_1e3(case):
+    """BF16 hi+lo products with FP32 accumulation: within 1e-3 (infinity-norm
+    relative) of the FP64 oracle fed the FP32 weights; the matrix unit's own
+    summation order makes bitwise parity unpinned."""
+    name, w, kind, shape, T, m = case
+    w = synth.to_f32_exact(w)
+    u0 = synth.grid_f32(shape)
+    print("case", name, shape, "T", T, "m", m, flush=True)
+    got = run_gpu(w, kind, u0, T, m, sf.STENCIL_MODE_MFMA_BF16X3)
+    ref64 = oracle.sweep(w, u0.astype(np.float64), T)
+    e = oracle.errors(got, ref64)
+    assert e["e_rel"] < 1e-3, e
+    # and it is a real split: much closer than single-BF16 rounding of the input
+    assert e["e_rel"] < 2.0 ** -12, e
+
+
+def test_mfma_rejects_unsupported():
+    plan = sf.Plan(synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX)
+    plan.fold(9)
+    plan.set_mode(sf.STENCIL_MODE_MFMA_BF16X3)
+    t = torch.zeros((64, 64), device=DEV)
+    with pytest.raises(sf.StencilError) as e:
+        plan.run(t, 9)
+    assert e.value.code == sf.STENCIL_E_UNSUPPORTED
+    plan.fold(2)
+    with pytest.raises(sf.StencilError) as e:
+        plan.run(torch.zeros((64, 64), device=DEV, dtype=torch.float64), 2)
+    assert e.value.code == sf.STENCIL_E_UNSUPPORTED
+    plan.close()
