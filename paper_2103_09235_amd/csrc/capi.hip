@@ -159,6 +159,15 @@ int check_plan(stencil_plan p) {
 
 }  // namespace
 
+void free_plan_devices(stencil_plan_s *p) {
+  int cur = 0;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  for (auto &kv : p->dev)
+    if (hipSetDevice(kv.first) == hipSuccess) free_device_state(kv.second);
+  p->dev.clear();
+  if (have) (void)hipSetDevice(cur);
+}
+
 }  // namespace stencil
 
 using namespace stencil;
@@ -445,12 +454,7 @@ int stencil_residual(const void *u, const void *ref, int dtype, int64_t n,
 
 void stencil_plan_destroy(stencil_plan p) {
   if (!p) return;
-  int cur = 0;
-  bool have = hipGetDevice(&cur) == hipSuccess;
-  for (auto &kv : p->dev) {
-    if (hipSetDevice(kv.first) == hipSuccess) free_device_state(kv.second);
-  }
-  if (have) (void)hipSetDevice(cur);
+  free_plan_devices(p);
   delete p;
 }
 

@@ -74,9 +74,13 @@ struct stencil_plan_s {
   std::vector<float> Wm32;    // folded FP32 weights (rounded, compensated)
   std::vector<uint16_t> Wm_hi, Wm_lo;  // bf16 split of Wm32
   std::map<int, stencil::DeviceState> dev;
+  std::map<int, std::vector<float>> batch_w32;  // folded FP32 weights by m (batched runs)
 };
 
 namespace stencil {
+
+// Free every device resource a plan holds (all devices); the plan stays valid.
+void free_plan_devices(stencil_plan_s *p);
 
 int side_of(int R);
 int64_t count_of(int dim, int R);

@@ -28,9 +28,18 @@
 namespace stencil {
 namespace k2d {
 
+// Weights passed by value in the kernel arguments (read through the
+// scalar cache), or from a uniform global pointer (batched tiles).
 template <typename T, int N>
 struct WArr {
   T v[N];
+  __device__ __forceinline__ T operator[](int i) const { return v[i]; }
+};
+
+template <typename T>
+struct WPtr {
+  const T *__restrict__ p;
+  __device__ __forceinline__ T operator[](int i) const { return p[i]; }
 };
 
 __device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -113,10 +122,12 @@ __host__ __device__ constexpr bool rotate_queue() {
   return (2 * R + 1) * mask_taps<MASK, R>() * VX <= 4096;
 }
 
-template <typename T, int R, int MASK, int VX, int PD>
-__global__ void __launch_bounds__(64)
-k_sweep2d(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
-          int tiles_y, int tiles_x, int xfast, WArr<T, (2 * R + 1) * (2 * R + 1)> W) {
+// One tile: output rows [y0, y1) of the column strip starting at x0, one
+// wavefront (64 lanes x VX columns), streaming input rows y0-R .. y1+R-1.
+template <typename T, int R, int MASK, int VX, int PD, typename WA>
+__device__ __forceinline__ void sweep2d_tile(const T *__restrict__ in, T *__restrict__ out,
+                                             int ny, int nx, int x0, int y0, int y1,
+                                             const WA &W) {
   constexpr int S = 2 * R + 1;
   constexpr int NU = S;
   constexpr bool ROT = rotate_queue<MASK, R, VX>();
@@ -128,16 +139,10 @@ k_sweep2d(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
   __shared__ T lds[2][LW];
 
   const int lane = threadIdx.x;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
-  // xfast: horizontally adjacent tiles are consecutive (they run together
-  // and share halo columns through L2); else vertically adjacent ones are.
-  const int tx = xfast ? t % tiles_x : t / tiles_y;
-  const int ty = xfast ? t / tiles_x : t - tx * tiles_y;
-  const int x0 = tx * BX, y0 = ty * BY;
   const int w = min(BX, nx - x0);
-  const int y1 = min(y0 + BY, ny);
   const bool valid = lane * VX < w;
   const int xl = x0 + lane * VX;
+  __syncthreads();  // a previous tile of this wavefront may still own the rows
 
   int hx = -1, hpos = 0;
   if (lane < R) {
@@ -215,7 +220,7 @@ k_sweep2d(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
 #pragma unroll
             for (int ox = -R; ox <= R; ++ox) {
               if (in_mask<MASK, R>(oy, ox)) {
-                const T wt = W.v[(oy + R) * S + (ox + R)];
+                const T wt = W[(oy + R) * S + (ox + R)];
 #pragma unroll
                 for (int v = 0; v < VX; ++v)
                   acc[slot][v] = fmat(wt, win[RP + v + ox], acc[slot][v]);
@@ -241,6 +246,21 @@ k_sweep2d(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
       }
     }
   }
+}
+
+template <typename T, int R, int MASK, int VX, int PD>
+__global__ void __launch_bounds__(64)
+k_sweep2d(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
+          int tiles_y, int tiles_x, int xfast, WArr<T, (2 * R + 1) * (2 * R + 1)> W) {
+  constexpr int BX = 64 * VX;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  // xfast: horizontally adjacent tiles are consecutive (they run together
+  // and share halo columns through L2); else vertically adjacent ones are.
+  const int tx = xfast ? t % tiles_x : t / tiles_y;
+  const int ty = xfast ? t / tiles_x : t - tx * tiles_y;
+  const int x0 = tx * BX, y0 = ty * BY;
+  const int y1 = min(y0 + BY, ny);
+  sweep2d_tile<T, R, MASK, VX, PD>(in, out, ny, nx, x0, y0, y1, W);
 }
 
 }  // namespace k2d

@@ -237,3 +237,80 @@ def test_mfma_rejects_unsupported():
         plan.run(torch.zeros((64, 64), device=DEV, dtype=torch.float64), 2)
     assert e.value.code == sf.STENCIL_E_UNSUPPORTED
     plan.close()
+
+
+# ----------------------------------------------------------- batched form
+
+def _batch_inputs(count, seed_sides):
+    sides, kinds, weights = synth.batched_recipe(count)
+    # replace a few sides to cover the vector path (multiple of 4, >= 256) and
+    # ragged small grids
+    sides = sides.copy()
+    sides[:3] = [256, 68, 301][: min(3, count)]
+    grids = [synth.grid_f32((int(s), int(s)), stream=5 + i % 3) for i, s in enumerate(sides)]
+    return sides, kinds, weights, grids
+
+
+def _run_batched(kinds, weights, grids, T, tune_cache=None, autotune=False, use_graph=True,
+                 max_m=1, repeats=1):
+    plans = [sf.Plan(w, sf.STENCIL_STAR if k == synth.STAR else sf.STENCIL_BOX)
+             for k, w in zip(kinds, weights)]
+    datas = [torch.from_numpy(g).to(DEV) for g in grids]
+    scr = [torch.empty_like(d) for d in datas]
+    chosen = None
+    for _ in range(repeats):
+        chosen = sf.stencil_run_batched([p.handle for p in plans], datas, scr, T,
+                                        autotune=autotune, tune_cache=tune_cache,
+                                        use_graph=use_graph, max_m=max_m)
+    torch.cuda.synchronize()
+    outs = [d.cpu().numpy() for d in datas]
+    for p in plans:
+        p.close()
+    return outs, chosen
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batched_plain_bit_exact(use_graph):
+    sides, kinds, weights, grids = _batch_inputs(12, 0)
+    T = 7  # odd: every grid ends after a copy-back
+    outs, chosen = _run_batched(kinds, weights, grids, T, use_graph=use_graph)
+    assert chosen == [1] * len(grids)
+    for g, w, o in zip(grids, weights, outs):
+        ref = oracle.folded_reference_f32(w, g, T, 1)
+        assert np.array_equal(o, ref)
+
+
+def test_batched_folded_from_tune_cache(tmp_path):
+    sides, kinds, weights, grids = _batch_inputs(10, 1)
+    cache = tmp_path / "tune.txt"
+    # fold depth 2 for every (shape, r = 1, size class) this batch has
+    lines = []
+    for shape in (0, 1):
+        for cls in range(5, 12):
+            lines.append("stencil-batched-m %d 1 %d 2" % (shape, cls))
+    cache.write_text("\n".join(lines) + "\n")
+    T = 9  # 4 folded + 1 plain sweep per grid
+    outs, chosen = _run_batched(kinds, weights, grids, T, tune_cache=str(cache), max_m=2)
+    assert chosen == [2] * len(grids)
+    for g, w, o in zip(grids, weights, outs):
+        ref = oracle.folded_reference_f32(w, g, T, 2)
+        assert np.array_equal(o, ref)
+
+
+def test_batched_graph_replay_composes():
+    sides, kinds, weights, grids = _batch_inputs(6, 2)
+    outs, _ = _run_batched(kinds, weights, grids, 4, repeats=3)
+    for g, w, o in zip(grids, weights, outs):
+        assert np.array_equal(o, oracle.folded_reference_f32(w, g, 12, 1))
+
+
+def test_batched_autotune_picks_valid_m(tmp_path):
+    sides, kinds, weights, grids = _batch_inputs(5, 3)
+    cache = tmp_path / "auto.txt"
+    T = 8
+    outs, chosen = _run_batched(kinds, weights, grids, T, tune_cache=str(cache), autotune=True,
+                                max_m=2)
+    assert all(m in (1, 2) for m in chosen)
+    assert cache.exists() and "stencil-batched-m" in cache.read_text()
+    for g, w, o, m in zip(grids, weights, outs, chosen):
+        assert np.array_equal(o, oracle.folded_reference_f32(w, g, T, m))
