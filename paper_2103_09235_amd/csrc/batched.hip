@@ -51,16 +51,19 @@ struct Tile {
   int grid, x0, y0, y1;
 };
 
-// variant = (R - 1) * 4 + (mask == DIAMOND) * 2 + (VX == 4)
+// variant = (R - 1) * 4 + (mask == DIAMOND) * 2 + (vector lanes)
 __host__ __device__ constexpr int variant_id(int R, bool diamond, bool vx4) {
   return (R - 1) * 4 + (diamond ? 2 : 0) + (vx4 ? 1 : 0);
 }
 
+// Variants: aligned rows of >= 256 floats use vector lanes (two rows of
+// look-ahead), the rest strided lanes (4 coalesced scalars per lane).
 __global__ void __launch_bounds__(64)
 k_batched(const Tile *__restrict__ tiles, int ntiles, const GridInfo *__restrict__ grids,
           const float *__restrict__ wtab, int k) {
   using k2d::sweep2d_tile;
   using k2d::WPtr;
+  __shared__ float lds[2 * k2d::lds_row<kMaxBatchRadius, 4>(0)];  // largest variant
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const Tile tl = tiles[t];
     const GridInfo g = grids[tl.grid];
@@ -72,28 +75,28 @@ k_batched(const Tile *__restrict__ tiles, int ntiles, const GridInfo *__restrict
     float *out = (k & 1) ? g.data : g.scratch;
     switch (var) {
       case variant_id(1, false, false):
-        sweep2d_tile<float, 1, MASK_BOX, 1, 1>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w);
+        sweep2d_tile<float, 1, MASK_BOX, 4, 1, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       case variant_id(1, false, true):
-        sweep2d_tile<float, 1, MASK_BOX, 4, 1>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w);
+        sweep2d_tile<float, 1, MASK_BOX, 4, 2, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       case variant_id(1, true, false):
-        sweep2d_tile<float, 1, MASK_DIAMOND, 1, 1>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w);
+        sweep2d_tile<float, 1, MASK_DIAMOND, 4, 1, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       case variant_id(1, true, true):
-        sweep2d_tile<float, 1, MASK_DIAMOND, 4, 1>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w);
+        sweep2d_tile<float, 1, MASK_DIAMOND, 4, 2, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       case variant_id(2, false, false):
-        sweep2d_tile<float, 2, MASK_BOX, 1, 1>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w);
+        sweep2d_tile<float, 2, MASK_BOX, 4, 1, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       case variant_id(2, false, true):
-        sweep2d_tile<float, 2, MASK_BOX, 4, 1>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w);
+        sweep2d_tile<float, 2, MASK_BOX, 4, 2, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       case variant_id(2, true, false):
-        sweep2d_tile<float, 2, MASK_DIAMOND, 1, 1>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w);
+        sweep2d_tile<float, 2, MASK_DIAMOND, 4, 1, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       default:
-        sweep2d_tile<float, 2, MASK_DIAMOND, 4, 1>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w);
+        sweep2d_tile<float, 2, MASK_DIAMOND, 4, 2, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
     }
   }
@@ -379,7 +382,7 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
       G.nx = (int)g.shape[1];
       G.q = m > 1 ? (int)(T / m) : 0;
       G.s = m > 1 ? (int)(T % m) : (int)T;
-      const bool vx4 = (G.nx % 4 == 0) && G.nx >= 256 && ((uintptr_t)g.data % 16 == 0) &&
+      const bool vx4 = (G.nx % 4 == 0) && ((uintptr_t)g.data % 16 == 0) &&
                        ((uintptr_t)g.scratch % 16 == 0);
       const bool star = p->shape == STENCIL_STAR;
       G.var_p = variant_id(p->r, star, vx4);
@@ -391,12 +394,12 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
       const int sweeps = G.q + G.s;
       launches = std::max(launches, sweeps);
       if (sweeps % 2) odd.push_back(i);
-      const int bx = vx4 ? 256 : 64;
+      const int bx = 256;
       const int R = m * p->r;
       for (int y0 = 0; y0 < G.ny; y0 += kTileRows)
         for (int x0 = 0; x0 < G.nx; x0 += bx) {
           const int y1 = std::min(G.ny, y0 + kTileRows);
-          const int64_t cost = (int64_t)(y1 - y0 + 2 * R) * (vx4 ? 4 : 1) * (2 * R + 1);
+          const int64_t cost = (int64_t)(y1 - y0 + 2 * R) * (2 * R + 1);
           tiles.push_back({cost, Tile{i, x0, y0, y1}});
         }
     }
@@ -409,7 +412,7 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
     b.launches = launches;
     hipDeviceProp_t prop;
     STENCIL_HIP_TRY(hipGetDeviceProperties(&prop, device));
-    b.nblocks = std::max(1, std::min(b.ntiles, prop.multiProcessorCount * 16));
+    b.nblocks = std::max(1, std::min(b.ntiles, prop.multiProcessorCount * 32));
     hipError_t e = hipMalloc(&b.d_tiles, sizeof(Tile) * tl.size());
     if (e == hipSuccess) e = hipMalloc(&b.d_grids, sizeof(GridInfo) * gi.size());
     if (e == hipSuccess) e = hipMalloc(&b.d_w, sizeof(float) * std::max<size_t>(1, wt.size()));

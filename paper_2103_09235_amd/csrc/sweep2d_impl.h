@@ -122,12 +122,24 @@ __host__ __device__ constexpr bool rotate_queue() {
   return (2 * R + 1) * mask_taps<MASK, R>() * VX <= 4096;
 }
 
+// LDS row width of a tile routine: 64*VX centre columns plus the halo
+// padded to whole vectors.
+template <int R, int VX>
+__host__ __device__ constexpr int lds_row(int) {
+  return 64 * VX + 2 * (((R + VX - 1) / VX) * VX);
+}
+
 // One tile: output rows [y0, y1) of the column strip starting at x0, one
-// wavefront (64 lanes x VX columns), streaming input rows y0-R .. y1+R-1.
-template <typename T, int R, int MASK, int VX, int PD, typename WA>
+// wavefront, streaming input rows y0-R .. y1+R-1.  A lane owns VX columns:
+// contiguous ones (STR = false, loaded as one vector; needs rows aligned to
+// VX) or the strided columns x0 + lane + 64v (STR = true, one coalesced
+// scalar load each; any row length).  Either way 64*VX columns per wave.
+// lds: 2 * lds_row<R, VX>() elements of workgroup memory, owned by the caller
+// (so several variants in one kernel can share one buffer).
+template <typename T, int R, int MASK, int VX, int PD, bool STR, typename WA>
 __device__ __forceinline__ void sweep2d_tile(const T *__restrict__ in, T *__restrict__ out,
                                              int ny, int nx, int x0, int y0, int y1,
-                                             const WA &W) {
+                                             const WA &W, T *lds) {
   constexpr int S = 2 * R + 1;
   constexpr int NU = S;
   constexpr bool ROT = rotate_queue<MASK, R, VX>();
@@ -136,11 +148,16 @@ __device__ __forceinline__ void sweep2d_tile(const T *__restrict__ in, T *__rest
   constexpr int BX = 64 * VX;
   constexpr int RP = ((R + VX - 1) / VX) * VX;
   constexpr int LW = BX + 2 * RP;
-  __shared__ T lds[2][LW];
+  static_assert(LW == lds_row<R, VX>(0), "lds row");
 
   const int lane = threadIdx.x;
   const int w = min(BX, nx - x0);
-  const bool valid = lane * VX < w;
+  // local column of element v and whether it lies inside the strip
+  auto col = [&](int v) { return STR ? lane + 64 * v : lane * VX + v; };
+  bool ok[VX];
+#pragma unroll
+  for (int v = 0; v < VX; ++v) ok[v] = col(v) < w;
+  const bool valid = ok[0];
   const int xl = x0 + lane * VX;
   __syncthreads();  // a previous tile of this wavefront may still own the rows
 
@@ -161,7 +178,17 @@ __device__ __forceinline__ void sweep2d_tile(const T *__restrict__ in, T *__rest
 
   const int jstart = y0 - R, jend = y1 + R;
 
-  // ring of PD rows of look-ahead (centre vector + halo element); row j
+  auto load_row = [&](const T *row, T (&d)[VX]) {
+    if constexpr (STR) {
+#pragma unroll
+      for (int v = 0; v < VX; ++v)
+        if (ok[v]) d[v] = __builtin_nontemporal_load(row + x0 + col(v));
+    } else {
+      if (valid) load_vec<T, VX>(row + xl, d);
+    }
+  };
+
+  // ring of PD rows of look-ahead (centre values + halo element); row j
   // sits in slot (j - jstart) % PD, a compile-time index in the unrolled loop
   T pf[PD][VX];
   T pfh[PD];
@@ -172,7 +199,7 @@ __device__ __forceinline__ void sweep2d_tile(const T *__restrict__ in, T *__rest
     for (int v = 0; v < VX; ++v) pf[d][v] = T(0);
     if (jstart + d < jend) {
       const T *row = in + (size_t)wrap1(jstart + d, ny) * nx;
-      if (valid) load_vec<T, VX>(row + xl, pf[d]);
+      load_row(row, pf[d]);
       if (hx >= 0) pfh[d] = row[hx];
     }
   }
@@ -188,54 +215,73 @@ __device__ __forceinline__ void sweep2d_tile(const T *__restrict__ in, T *__rest
         const T curh = pfh[u % PD];
         if (j + PD < jend) {
           const T *row = in + (size_t)wrap1(j + PD, ny) * nx;
-          if (valid) load_vec<T, VX>(row + xl, pf[u % PD]);
+          load_row(row, pf[u % PD]);
           if (hx >= 0) pfh[u % PD] = row[hx];
         }
-        T *L = lds[(j - jstart) & 1];
-        if (valid) store_vec<T, VX>(L + RP + lane * VX, cur);
+        T *L = lds + ((j - jstart) & 1) * LW;
+        if constexpr (STR) {
+#pragma unroll
+          for (int v = 0; v < VX; ++v)
+            if (ok[v]) L[RP + col(v)] = cur[v];
+        } else {
+          if (valid) store_vec<T, VX>(L + RP + lane * VX, cur);
+        }
         if (hx >= 0) L[hpos] = curh;
         __syncthreads();
-        // window: win[i] = value at x = xl + i - RP, i in [RP-R, RP+VX+R)
-        T win[VX + 2 * RP];
+        // win[v][ox + R] = value at column col(v) + ox (strided), or
+        // win[0][i] = value at x = xl + i - RP (contiguous)
+        constexpr int WN = STR ? S : VX + 2 * RP;
+        constexpr int WV = STR ? VX : 1;
+        T win[WV][WN];
+        if constexpr (STR) {
 #pragma unroll
-        for (int i = 0; i < RP; ++i) {
-          if (i >= RP - R) win[i] = L[lane * VX + i];
-          else win[i] = T(0);
-        }
+          for (int v = 0; v < VX; ++v)
 #pragma unroll
-        for (int v = 0; v < VX; ++v) win[RP + v] = cur[v];
+            for (int i = 0; i < S; ++i)
+              win[v][i] = (i == R) ? cur[v] : L[RP + col(v) + i - R];
+        } else {
 #pragma unroll
-        for (int i = RP + VX; i < VX + 2 * RP; ++i) {
-          if (i < RP + VX + R) win[i] = L[lane * VX + i];
-          else win[i] = T(0);
+          for (int i = 0; i < RP; ++i) win[0][i] = (i >= RP - R) ? L[lane * VX + i] : T(0);
+#pragma unroll
+          for (int v = 0; v < VX; ++v) win[0][RP + v] = cur[v];
+#pragma unroll
+          for (int i = RP + VX; i < VX + 2 * RP; ++i)
+            win[0][i] = (i < RP + VX + R) ? L[lane * VX + i] : T(0);
         }
 #pragma unroll
         for (int k = S - 1; k >= 0; --k) {
           // pending output row y = j - R + k receives weight row oy = R - k
           // (rows outside [y0, y1) accumulate too and are simply never
           // stored: cheaper than a branch per pending row)
-          {
-            const int slot = ROT ? (u + k) % NU : k;
-            const int oy = R - k;
+          const int slot = ROT ? (u + k) % NU : k;
+          const int oy = R - k;
 #pragma unroll
-            for (int ox = -R; ox <= R; ++ox) {
-              if (in_mask<MASK, R>(oy, ox)) {
-                const T wt = W[(oy + R) * S + (ox + R)];
+          for (int ox = -R; ox <= R; ++ox) {
+            if (in_mask<MASK, R>(oy, ox)) {
+              const T wt = W[(oy + R) * S + (ox + R)];
 #pragma unroll
-                for (int v = 0; v < VX; ++v)
-                  acc[slot][v] = fmat(wt, win[RP + v + ox], acc[slot][v]);
-              }
+              for (int v = 0; v < VX; ++v)
+                acc[slot][v] = fmat(wt, STR ? win[v % WV][ox + R] : win[0][RP + v + ox], acc[slot][v]);
             }
           }
         }
         // output row j - R is complete
         const int yd = j - R;
+        T(&done)[VX] = acc[ROT ? u % NU : 0];
+        if (yd >= y0) {
+          T *dst = out + (size_t)yd * nx;
+          if constexpr (STR) {
+#pragma unroll
+            for (int v = 0; v < VX; ++v)
+              if (ok[v]) __builtin_nontemporal_store(done[v], dst + x0 + col(v));
+          } else {
+            if (valid) store_vec<T, VX>(dst + xl, done);
+          }
+        }
         if constexpr (ROT) {
-          if (yd >= y0 && valid) store_vec<T, VX>(out + (size_t)yd * nx + xl, acc[u % NU]);
 #pragma unroll
           for (int v = 0; v < VX; ++v) acc[u % NU][v] = T(0);
         } else {
-          if (yd >= y0 && valid) store_vec<T, VX>(out + (size_t)yd * nx + xl, acc[0]);
 #pragma unroll
           for (int k = 0; k + 1 < NU; ++k)
 #pragma unroll
@@ -248,7 +294,7 @@ __device__ __forceinline__ void sweep2d_tile(const T *__restrict__ in, T *__rest
   }
 }
 
-template <typename T, int R, int MASK, int VX, int PD>
+template <typename T, int R, int MASK, int VX, int PD, bool STR>
 __global__ void __launch_bounds__(64)
 k_sweep2d(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
           int tiles_y, int tiles_x, int xfast, WArr<T, (2 * R + 1) * (2 * R + 1)> W) {
@@ -260,7 +306,8 @@ k_sweep2d(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
   const int ty = xfast ? t / tiles_x : t - tx * tiles_y;
   const int x0 = tx * BX, y0 = ty * BY;
   const int y1 = min(y0 + BY, ny);
-  sweep2d_tile<T, R, MASK, VX, PD>(in, out, ny, nx, x0, y0, y1, W);
+  __shared__ T lds[2 * lds_row<R, VX>(0)];
+  sweep2d_tile<T, R, MASK, VX, PD, STR>(in, out, ny, nx, x0, y0, y1, W, lds);
 }
 
 }  // namespace k2d

@@ -10,7 +10,7 @@
 namespace stencil {
 namespace k2d {
 
-template <typename T, int R, int MASK, int VX, int PD>
+template <typename T, int R, int MASK, int VX, int PD, bool STR>
 hipError_t launch_one(const SweepLaunch &L, const std::vector<T> &w) {
   constexpr int S = 2 * R + 1;
   constexpr int BX = 64 * VX;
@@ -37,7 +37,7 @@ hipError_t launch_one(const SweepLaunch &L, const std::vector<T> &w) {
     return e ? std::atoi(e) : -1;
   }();
   const int xfast = order_env >= 0 ? order_env : (R >= 3 ? 1 : 0);
-  hipLaunchKernelGGL((k_sweep2d<T, R, MASK, VX, PD>), dim3((unsigned)blocks), dim3(64), 0,
+  hipLaunchKernelGGL((k_sweep2d<T, R, MASK, VX, PD, STR>), dim3((unsigned)blocks), dim3(64), 0,
                      L.stream, (const T *)L.in, (T *)L.out, ny, nx, by, tiles_y, tiles_x,
                      xfast, W);
   return hipGetLastError();
@@ -48,17 +48,18 @@ hipError_t launch_vx(const SweepLaunch &L, const std::vector<T> &w) {
   constexpr int VXW = 16 / sizeof(T);
   const bool aligned = ((uintptr_t)L.in % 16 == 0) && ((uintptr_t)L.out % 16 == 0) &&
                        (L.g.nx % VXW == 0);
-  if (!aligned) return launch_one<T, R, MASK, 1, 1>(L, w);
+  // rows that are not whole vectors: strided lanes (coalesced scalars)
+  if (!aligned) return launch_one<T, R, MASK, VXW, 1, true>(L, w);
   if constexpr (R <= 2 && rotate_queue<MASK, R, VXW>()) {
     // two rows of look-ahead measured best on gfx950 (STENCIL_PD overrides)
     static const int pd = [] {
       const char *e = std::getenv("STENCIL_PD");
       return e ? std::atoi(e) : 2;
     }();
-    if (pd == 2) return launch_one<T, R, MASK, VXW, 2>(L, w);
-    if (pd == 4) return launch_one<T, R, MASK, VXW, 4>(L, w);
+    if (pd == 2) return launch_one<T, R, MASK, VXW, 2, false>(L, w);
+    if (pd == 4) return launch_one<T, R, MASK, VXW, 4, false>(L, w);
   }
-  return launch_one<T, R, MASK, VXW, 1>(L, w);
+  return launch_one<T, R, MASK, VXW, 1, false>(L, w);
 }
 
 template <typename T, int R>
