@@ -1,0 +1,163 @@
+"""GPU parity at the measured workloads' full sizes, in the launch
+configurations bench.py times.
+
+The oracle cannot sweep a 16384^2 grid for hundreds of steps, so:
+  * sampled outputs of short runs are computed one by one by the oracle on
+    each sample's dependency window (the FP32 mirror of the same schedule, so
+    vector kernels must match bit for bit; the matrix-core form within 1e-3 of
+    the FP64 sweep);
+  * long runs are checked through properties that hold at any size: mass
+    (sum w)^T sum u0 against the FP64 compensated GPU sum, and bitwise
+    translation equivariance of the whole grid.
+"""
+
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2103_09235_amd as sf  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+@functools.lru_cache(maxsize=2)
+def full_grid(name):
+    return synth.grid_f32(synth.WORKLOADS[name].shape)
+
+
+def window(u0, p, reach):
+    idx = [(int(c) + np.arange(-reach, reach + 1)) % n for c, n in zip(p, u0.shape)]
+    return u0[np.ix_(*idx)]
+
+
+def sampled_points(shape, k, seed):
+    rng = np.random.default_rng(seed)
+    pts = [tuple(int(rng.integers(0, n)) for n in shape) for _ in range(k)]
+    pts.append(tuple(0 for _ in shape))
+    pts.append(tuple(n - 1 for n in shape))
+    return pts
+
+
+def run(w, kind, u0, T, m, mode=sf.STENCIL_MODE_VECTOR):
+    plan = sf.Plan(w, kind)
+    if m > 1:
+        plan.fold(m)
+    plan.set_mode(mode)
+    d = torch.from_numpy(u0).to(DEV)
+    s = torch.empty_like(d)
+    plan.run(d, T, s)
+    torch.cuda.synchronize()
+    plan.close()
+    return d
+
+
+@pytest.mark.parametrize("name,m,T,mode", [
+    ("star2d", 1, 6, "vector"), ("star2d", 2, 6, "vector"), ("star2d", 4, 8, "vector"),
+    ("box2d", 4, 8, "vector"), ("box2d", 8, 8, "vector"), ("box2d", 4, 8, "mfma"),
+    ("box2d", 8, 16, "mfma"), ("star3d", 2, 4, "vector"), ("box3d", 2, 4, "vector"),
+    ("box3d", 1, 3, "vector"),
+])
+def test_sampled_outputs_full_size(name, m, T, mode):
+    wl = synth.WORKLOADS[name]
+    print("full size", name, wl.shape, "m", m, "T", T, mode, flush=True)
+    u0 = full_grid(name)
+    mcode = sf.STENCIL_MODE_MFMA_BF16X3 if mode == "mfma" else sf.STENCIL_MODE_VECTOR
+    d = run(wl.weights, wl.shape_kind, u0, T, m, mcode)
+    pts = sampled_points(wl.shape, 40, hash((name, m)) % 1000)
+    got = np.array([d[p].item() for p in pts], dtype=np.float32)
+    reach = T * ((wl.weights.shape[0] - 1) // 2)
+    centre = tuple([reach] * len(wl.shape))
+    if mode == "vector":
+        ref = np.array([oracle.folded_reference_f32(wl.weights, window(u0, p, reach), T, m)[centre]
+                        for p in pts], dtype=np.float32)
+        assert np.array_equal(got, ref)
+    ref64 = np.array([oracle.sweep(wl.weights, window(u0, p, reach).astype(np.float64), T)[centre]
+                      for p in pts])
+    err = np.max(np.abs(got - ref64)) / np.max(np.abs(ref64))
+    assert err < (1e-3 if mode == "mfma" else 1e-5), err
+
+
+@pytest.mark.parametrize("name,m", [("star2d", 4), ("star2d", 1), ("star3d", 2), ("box2d", 8)])
+def test_long_run_mass_full_size(name, m):
+    """Full T: total mass equals (sum w)^T times the initial mass to within
+    the FP32 rounding the run can accumulate (bound derived below)."""
+    wl = synth.WORKLOADS[name]
+    u0 = full_grid(name)
+    d = torch.from_numpy(u0).to(DEV)
+    s0 = sf.stencil_residual(d)[0]
+    plan = sf.Plan(wl.weights, wl.shape_kind)
+    if m > 1:
+        plan.fold(m)
+    s = torch.empty_like(d)
+    plan.run(d, wl.T, s)
+    torch.cuda.synchronize()
+    s1 = sf.stencil_residual(d)[0]
+    plan.close()
+    sw = math.fsum(wl.weights.ravel().tolist())
+    expect = sw ** wl.T * s0
+    # each sweep rounds every output once per tap (relative 2^-24 each,
+    # unbiased): the mean mass error of N points grows like
+    # sweeps * taps * 2^-24 / sqrt(N); allow a bias of 2^-24 per sweep on top
+    sweeps = wl.T // m + wl.T % m
+    bound = sweeps * 2.0 ** -24 * 4
+    assert abs(s1 - expect) / abs(expect) < bound, (s1, expect, bound)
+
+
+@pytest.mark.parametrize("name,m", [("star2d", 4), ("box3d", 2)])
+def test_translation_equivariance_full_size(name, m):
+    wl = synth.WORKLOADS[name]
+    u0 = full_grid(name)
+    shift = tuple(n // 3 + 1 for n in wl.shape)
+    axes = tuple(range(len(wl.shape)))
+    T = 2 * m + 1
+    a = run(wl.weights, wl.shape_kind, np.ascontiguousarray(np.roll(u0, shift, axes)), T, m)
+    b = run(wl.weights, wl.shape_kind, u0, T, m)
+    assert torch.equal(a, torch.roll(b, shift, axes))
+
+
+def test_heat1d_full_size_bit_exact_fp64():
+    wl = synth.WORKLOADS["heat1d"]
+    u0 = synth.grid_f64(wl.shape)
+    d = run(wl.weights, wl.shape_kind, u0, wl.T, 1)
+    ref = oracle.sweep(wl.weights, u0, wl.T)
+    assert np.array_equal(d.cpu().numpy(), ref)
+
+
+def test_batched_full_size_sampled_grids(tmp_path):
+    """The 4096-grid batch as bench.py runs it (autotuned m <= 2, graph):
+    16 grids checked whole against the oracle's FP32 mirror of their fold
+    depth."""
+    count, T = 4096, 50
+    sides, kinds, weights = synth.batched_recipe(count)
+    npts = int(np.sum(sides.astype(np.int64) ** 2))
+    flat = synth.uniform_f32(synth.SEED, synth.STREAM_GRID, npts)
+    u0s, off = [], 0
+    for s in sides:
+        n = int(s) * int(s)
+        u0s.append(flat[off:off + n].reshape(int(s), int(s)))
+        off += n
+    datas = [torch.from_numpy(u).to(DEV) for u in u0s]
+    scr = [torch.empty_like(d) for d in datas]
+    plans = [sf.Plan(w, sf.STENCIL_STAR if k == synth.STAR else sf.STENCIL_BOX)
+             for k, w in zip(kinds, weights)]
+    chosen = sf.stencil_run_batched([p.handle for p in plans], datas, scr, T, autotune=True,
+                                    tune_cache=str(tmp_path / "t.txt"), use_graph=True, max_m=2)
+    torch.cuda.synchronize()
+    order = np.argsort(sides)
+    pick = list(order[:10]) + list(order[count // 2: count // 2 + 4]) + list(order[-2:])
+    for i in pick:
+        ref = oracle.folded_reference_f32(weights[i], u0s[i], T, chosen[i])
+        assert np.array_equal(datas[i].cpu().numpy(), ref), (i, int(sides[i]), chosen[i])
+    for p in plans:
+        p.close()
