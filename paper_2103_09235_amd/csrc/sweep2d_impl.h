@@ -62,11 +62,15 @@ struct Vec {
 // hints; on gfx950 this raises streaming bandwidth by about a tenth.
 template <typename T, int VX>
 __device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&d)[VX]) {
-  if constexpr (VX * sizeof(T) == 16) {
-    using V = __attribute__((ext_vector_type(16 / sizeof(T)))) T;
-    V t = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+  if constexpr (VX * sizeof(T) % 16 == 0) {
+    constexpr int E = 16 / sizeof(T);  // elements per 16-byte chunk
+    using V = __attribute__((ext_vector_type(E))) T;
 #pragma unroll
-    for (int i = 0; i < VX; ++i) d[i] = t[i];
+    for (int c = 0; c < VX / E; ++c) {
+      V t = __builtin_nontemporal_load(reinterpret_cast<const V *>(p + c * E));
+#pragma unroll
+      for (int i = 0; i < E; ++i) d[c * E + i] = t[i];
+    }
   } else if constexpr (VX * sizeof(T) == 8) {
     using V = __attribute__((ext_vector_type(8 / sizeof(T)))) T;
     V t = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
@@ -80,12 +84,16 @@ __device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&d)[VX]) {
 
 template <typename T, int VX>
 __device__ __forceinline__ void store_vec(T *__restrict__ p, const T (&s)[VX]) {
-  if constexpr (VX * sizeof(T) == 16) {
-    using V = __attribute__((ext_vector_type(16 / sizeof(T)))) T;
-    V t;
+  if constexpr (VX * sizeof(T) % 16 == 0) {
+    constexpr int E = 16 / sizeof(T);
+    using V = __attribute__((ext_vector_type(E))) T;
 #pragma unroll
-    for (int i = 0; i < VX; ++i) t[i] = s[i];
-    __builtin_nontemporal_store(t, reinterpret_cast<V *>(p));
+    for (int c = 0; c < VX / E; ++c) {
+      V t;
+#pragma unroll
+      for (int i = 0; i < E; ++i) t[i] = s[c * E + i];
+      __builtin_nontemporal_store(t, reinterpret_cast<V *>(p + c * E));
+    }
   } else if constexpr (VX * sizeof(T) == 8) {
     using V = __attribute__((ext_vector_type(8 / sizeof(T)))) T;
     V t;

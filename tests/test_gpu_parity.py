@@ -52,6 +52,8 @@ CASES_2D = [
     ("star2d_min_m4", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (9, 9), 9, 4),
     ("star2d_aligned", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (256, 512), 5, 1),
     ("box2d_aligned_m2", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (128, 1024), 6, 2),
+    ("star2d_aligned_m4", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (136, 2048), 12, 4),
+    ("star2d_aligned_m3", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (72, 520), 9, 3),
 ]
 
 CASES_3D = [
