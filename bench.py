@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only-m", type=int, default=0,
                     help="time only this fold depth (profiling runs)")
+    ap.add_argument("--only-mode", default="", choices=["", "vector", "mfma_bf16x3"],
+                    help="time only this kernel family (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy (PMC byte-counter calibration)")
     return ap.parse_args()
@@ -177,6 +179,8 @@ def bench_grid(args, wl_name):
         if wl_name == "box2d" and m > 1 and hasattr(sf, "STENCIL_MODE_MFMA_BF16X3"):
             form_modes.append(("mfma_bf16x3", sf.STENCIL_MODE_MFMA_BF16X3))
         for mode_name, mode in form_modes:
+            if args.only_mode and mode_name != args.only_mode:
+                continue
             plan = sf.Plan(w, wl.shape_kind)
             if m > 1:
                 plan.fold(m)
