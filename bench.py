@@ -53,6 +53,8 @@ def parse():
                     help="time only this fold depth (profiling runs)")
     ap.add_argument("--only-mode", default="", choices=["", "vector", "mfma_bf16x3"],
                     help="time only this kernel family (profiling runs)")
+    ap.add_argument("--no-per-grid", action="store_true",
+                    help="batched: skip the per-grid-launch baseline (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy (PMC byte-counter calibration)")
     return ap.parse_args()
@@ -337,13 +339,15 @@ def bench_batched(args):
     log("[bench] persistent + graph, m = 1")
     t_m1 = run_form("persistent_graph_m1", lambda: sf.stencil_run_batched(
         handles, datas, scr, T, use_graph=True, max_m=1), args.steps, args.warmup)
-    log("[bench] per-grid launches (4096 x stencil_run, m = 1)")
     stream = torch.cuda.current_stream(dev)
 
     def per_grid():
         for p, d, s in zip(plans, datas, scr):
             sf.stencil_run(p.handle, d, T, s, stream)
-    t_pg = run_form("per_grid_launches_m1", per_grid, 1, 0)
+    t_pg = None
+    if not args.no_per_grid:
+        log("[bench] per-grid launches (4096 x stencil_run, m = 1)")
+        t_pg = run_form("per_grid_launches_m1", per_grid, 1, 0)
     # correctness of the headline form: mass of every grid after one run
     reset()
     s0 = [sf.stencil_residual(d)[0] for d in datas[:64]]
@@ -381,7 +385,7 @@ def bench_batched(args):
                    "fold_m_histogram": {str(m): int(sum(1 for x in ms if x == m)) for m in sorted(set(ms))}},
         "roofline": roof,
         "forms": forms,
-        "speedup_vs_per_grid_launches": round(t_pg / t_tuned, 2),
+        "speedup_vs_per_grid_launches": round(t_pg / t_tuned, 2) if t_pg else None,
         "speedup_tuned_vs_m1": round(t_m1 / t_tuned, 3),
         "mass_rel_drift_max_64_grids": drift,
     }

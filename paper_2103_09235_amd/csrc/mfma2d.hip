@@ -74,6 +74,7 @@ k_mfma2d(const float *__restrict__ in, float *__restrict__ out, int ny, int nx, 
   constexpr int PER = VEC ? PERV : PERS;
   __shared__ __attribute__((aligned(16))) unsigned short s_hi[kRing][SWP];
   __shared__ __attribute__((aligned(16))) unsigned short s_lo[kRing][SWP];
+  __shared__ __attribute__((aligned(16))) float s_out[16][kStrip + 4];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -213,16 +214,32 @@ k_mfma2d(const float *__restrict__ in, float *__restrict__ out, int ny, int nx, 
         acc_hh[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bhi[d], acc_hh[b], 0, 0, 0);
       }
     }
-    // D fragment: lane holds column li, rows 4*lg + j
+    // D fragment: lane holds column li, rows 4*lg + j.  The workgroup's
+    // 16 x kStrip output tile goes through LDS so that rows leave as whole
+    // 16-byte groups (scattered 4-byte stores of 16-lane rows cost about a
+    // third more HBM write traffic).
 #pragma unroll
     for (int b = 0; b < kBlocks; ++b) {
-      const int xo = x0 + 16 * (kBlocks * wave + b) + li;
-      if (xo < nx) {
+      const int oc = 16 * (kBlocks * wave + b) + li;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int yo = ybase + 16 * c + 4 * lg + j;
-          const float v = (acc_lh[b][j] + acc_hl[b][j]) + acc_hh[b][j];
-          if (yo < yend) __builtin_nontemporal_store(v, out + (size_t)yo * nx + xo);
+      for (int j = 0; j < 4; ++j)
+        s_out[4 * lg + j][oc] = (acc_lh[b][j] + acc_hl[b][j]) + acc_hh[b][j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < (16 * kStrip / 4) / kThreads; ++p) {
+      const int e = tid + p * kThreads;
+      const int r = e / (kStrip / 4), q = e - r * (kStrip / 4);
+      const int yo = ybase + 16 * c + r, xo = x0 + 4 * q;
+      if (yo < yend) {
+        float *dst = out + (size_t)yo * nx + xo;
+        const f32x4 v = *reinterpret_cast<const f32x4 *>(&s_out[r][4 * q]);
+        if (VEC && xo + 4 <= nx) {
+          __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(dst));
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (xo + t < nx) __builtin_nontemporal_store(v[t], dst + t);
         }
       }
     }
@@ -245,7 +262,7 @@ hipError_t launch_r(const SweepLaunch &L) {
   const int tiles_y = (ny + rows - 1) / rows;
   const int64_t blocks = (int64_t)tiles_x * tiles_y;
   if (blocks > (1LL << 31) - 1 || !L.op->mfma_b) return hipErrorNotSupported;
-  const bool vec = (nx % 4 == 0) && ((uintptr_t)L.in % 16 == 0);
+  const bool vec = (nx % 4 == 0) && ((uintptr_t)L.in % 16 == 0) && ((uintptr_t)L.out % 16 == 0);
   const uint4 *bt = (const uint4 *)L.op->mfma_b;
   const dim3 grid((unsigned)blocks), blk(kThreads);
   if (vec)
