@@ -45,7 +45,11 @@ enum { STENCIL_F32 = 0, STENCIL_F64 = 1 };            /* grid element type   */
 enum {
   STENCIL_MODE_VECTOR = 0,      /* tiled vector kernels (default)            */
   STENCIL_MODE_EXACT_ORDER = 1, /* one thread per point, canonical order     */
-  STENCIL_MODE_MFMA_BF16X3 = 2  /* 2D box folds as BF16 hi+lo MFMA products  */
+  STENCIL_MODE_MFMA_BF16X3 = 2, /* 2D box folds as BF16 hi+lo MFMA products */
+  STENCIL_MODE_SYMMETRIC = 3    /* 2D operators symmetric in x and y: mirrored
+                                   inputs summed once and each row's partial
+                                   sum shared by two output rows (Section 3.3,
+                                   Eq. 4-6); other operators run as VECTOR   */
 };
 enum {
   STENCIL_OK = 0,
@@ -119,6 +123,11 @@ int stencil_fold_weights_f32(stencil_plan p, float *out, int64_t *out_len);
 /*
  * stencil_plan_set_mode -- choose the kernel family (STENCIL_MODE_*).
  * MFMA_BF16X3 requires a 2D plan; runs with it accept FP32 grids only.
+ * SYMMETRIC requires a 2D plan; it applies to operators with
+ * w[dy][dx] == w[dy][-dx] == w[-dy][dx] on grids whose rows are whole
+ * 16-byte vectors, and otherwise runs the VECTOR kernels.  VECTOR and
+ * EXACT_ORDER keep the canonical summation order (acc = +0, one FMA per tap,
+ * row-major offsets); MFMA_BF16X3 and SYMMETRIC do not.
  * Errors: E_ARG, E_UNSUPPORTED.
  */
 int stencil_plan_set_mode(stencil_plan p, int mode);

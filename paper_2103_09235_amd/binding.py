@@ -19,6 +19,7 @@ STENCIL_STAR, STENCIL_BOX = 0, 1
 STENCIL_PERIODIC, STENCIL_DIRICHLET = 0, 1
 STENCIL_F32, STENCIL_F64 = 0, 1
 STENCIL_MODE_VECTOR, STENCIL_MODE_EXACT_ORDER, STENCIL_MODE_MFMA_BF16X3 = 0, 1, 2
+STENCIL_MODE_SYMMETRIC = 3
 STENCIL_OK = 0
 STENCIL_E_ARG = -1
 STENCIL_E_UNSUPPORTED = -2

@@ -75,28 +75,28 @@ k_batched(const Tile *__restrict__ tiles, int ntiles, const GridInfo *__restrict
     float *out = (k & 1) ? g.data : g.scratch;
     switch (var) {
       case variant_id(1, false, false):
-        sweep2d_tile<float, 1, MASK_BOX, 4, 1, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
+        sweep2d_tile<float, 1, MASK_BOX, 4, 1, true, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       case variant_id(1, false, true):
-        sweep2d_tile<float, 1, MASK_BOX, 4, 2, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
+        sweep2d_tile<float, 1, MASK_BOX, 4, 2, false, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       case variant_id(1, true, false):
-        sweep2d_tile<float, 1, MASK_DIAMOND, 4, 1, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
+        sweep2d_tile<float, 1, MASK_DIAMOND, 4, 1, true, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       case variant_id(1, true, true):
-        sweep2d_tile<float, 1, MASK_DIAMOND, 4, 2, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
+        sweep2d_tile<float, 1, MASK_DIAMOND, 4, 2, false, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       case variant_id(2, false, false):
-        sweep2d_tile<float, 2, MASK_BOX, 4, 1, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
+        sweep2d_tile<float, 2, MASK_BOX, 4, 1, true, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       case variant_id(2, false, true):
-        sweep2d_tile<float, 2, MASK_BOX, 4, 2, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
+        sweep2d_tile<float, 2, MASK_BOX, 4, 2, false, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       case variant_id(2, true, false):
-        sweep2d_tile<float, 2, MASK_DIAMOND, 4, 1, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
+        sweep2d_tile<float, 2, MASK_DIAMOND, 4, 1, true, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
       default:
-        sweep2d_tile<float, 2, MASK_DIAMOND, 4, 2, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
+        sweep2d_tile<float, 2, MASK_DIAMOND, 4, 2, false, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
         break;
     }
   }

@@ -96,6 +96,17 @@ int build_operator(const std::vector<T> &w, int dim, int R, int mask,
   if (!taps.empty())
     STENCIL_HIP_TRY(hipMemcpy(op.taps_dev, taps.data(), sizeof(int4) * taps.size(),
                               hipMemcpyHostToDevice));
+  if (dim == 2) {
+    op.symmetric = true;
+    for (int a = 0; a < s && op.symmetric; ++a)
+      for (int b = 0; b < s; ++b) {
+        const T v = w[(size_t)a * s + b];
+        if (v != w[(size_t)a * s + (s - 1 - b)] || v != w[(size_t)(s - 1 - a) * s + b]) {
+          op.symmetric = false;
+          break;
+        }
+      }
+  }
   if constexpr (sizeof(T) == 4) {
     op.w32.assign(w.begin(), w.end());
     if (dim == 2 && R <= 8) {
@@ -142,7 +153,11 @@ hipError_t dispatch(stencil_plan p, const SweepLaunch &L) {
   if (p->mode == STENCIL_MODE_MFMA_BF16X3) return launch_mfma2d(L);
   hipError_t e = hipErrorNotSupported;
   if (L.g.dim == 1) e = launch_sweep1d(L);
-  else if (L.g.dim == 2) e = launch_sweep2d(L);
+  else if (L.g.dim == 2) {
+    SweepLaunch Ls = L;
+    Ls.sym = p->mode == STENCIL_MODE_SYMMETRIC;
+    e = launch_sweep2d(Ls);
+  }
   else e = launch_sweep3d(L);
   if (e == hipErrorNotSupported) {
     if (L.steps != 1) return hipErrorNotSupported;
@@ -278,8 +293,10 @@ int stencil_plan_set_mode(stencil_plan p, int mode) {
   set_error("");
   if (int rc = check_plan(p)) return rc;
   if (mode != STENCIL_MODE_VECTOR && mode != STENCIL_MODE_EXACT_ORDER &&
-      mode != STENCIL_MODE_MFMA_BF16X3)
+      mode != STENCIL_MODE_MFMA_BF16X3 && mode != STENCIL_MODE_SYMMETRIC)
     return fail(STENCIL_E_ARG, "unknown mode");
+  if (mode == STENCIL_MODE_SYMMETRIC && p->dim != 2)
+    return fail(STENCIL_E_UNSUPPORTED, "SYMMETRIC mode needs a 2D plan");
   if (mode == STENCIL_MODE_MFMA_BF16X3 && p->dim != 2)
     return fail(STENCIL_E_UNSUPPORTED, "MFMA mode needs a 2D plan");
   p->mode = mode;

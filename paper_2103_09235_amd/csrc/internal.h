@@ -51,6 +51,7 @@ struct OperatorDev {
   std::vector<float> w32;    // host copies for by-value kernel arguments
   std::vector<double> w64;
   void *mfma_b = nullptr;    // BF16 hi/lo B-fragment table (2D FP32, R <= 8)
+  bool symmetric = false;    // 2D: w[dy][dx] == w[dy][-dx] == w[-dy][dx]
 };
 
 // Per-device state owned by a plan.
@@ -103,6 +104,7 @@ struct SweepLaunch {
   int dtype = STENCIL_F32;
   const OperatorDev *op = nullptr;
   int steps = 1;       // operator applications fused into this launch
+  bool sym = false;    // mode SYMMETRIC: share mirrored partial sums if the operator allows
   hipStream_t stream = nullptr;
 };
 

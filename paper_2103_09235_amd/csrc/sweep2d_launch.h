@@ -10,7 +10,7 @@
 namespace stencil {
 namespace k2d {
 
-template <typename T, int R, int MASK, int VX, int PD, bool STR>
+template <typename T, int R, int MASK, int VX, int PD, bool STR, bool SYM = false>
 hipError_t launch_one(const SweepLaunch &L, const std::vector<T> &w) {
   constexpr int S = 2 * R + 1;
   constexpr int BX = 64 * VX;
@@ -37,7 +37,7 @@ hipError_t launch_one(const SweepLaunch &L, const std::vector<T> &w) {
     return e ? std::atoi(e) : -1;
   }();
   const int xfast = order_env >= 0 ? order_env : (R >= 3 ? 1 : 0);
-  hipLaunchKernelGGL((k_sweep2d<T, R, MASK, VX, PD, STR>), dim3((unsigned)blocks), dim3(64), 0,
+  hipLaunchKernelGGL((k_sweep2d<T, R, MASK, VX, PD, STR, SYM>), dim3((unsigned)blocks), dim3(64), 0,
                      L.stream, (const T *)L.in, (T *)L.out, ny, nx, by, tiles_y, tiles_x,
                      xfast, W);
   return hipGetLastError();
@@ -50,6 +50,11 @@ hipError_t launch_vx(const SweepLaunch &L, const std::vector<T> &w) {
                        (L.g.nx % VXW == 0);
   // rows that are not whole vectors: strided lanes (coalesced scalars)
   if (!aligned) return launch_one<T, R, MASK, VXW, 1, true>(L, w);
+  // mirror-symmetric operators may share partial sums (mode SYMMETRIC)
+  if (L.sym && L.op->symmetric) {
+    if constexpr (R <= 2) return launch_one<T, R, MASK, VXW, 2, false, true>(L, w);
+    else return launch_one<T, R, MASK, VXW, 1, false, true>(L, w);
+  }
   // (eight columns per lane for the 41-tap fold measured 16% slower than
   // four: the larger register file halves occupancy)
   if constexpr (R <= 2 && rotate_queue<MASK, R, VXW>()) {

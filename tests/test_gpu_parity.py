@@ -316,3 +316,37 @@ def test_batched_autotune_picks_valid_m(tmp_path):
     assert cache.exists() and "stencil-batched-m" in cache.read_text()
     for g, w, o, m in zip(grids, weights, outs, chosen):
         assert np.array_equal(o, oracle.folded_reference_f32(w, g, T, m))
+
+
+# ------------------------------------------- shared-partial-sum (symmetric)
+
+def _symmetric_box():
+    w = synth.random_positive_weights(2, 1)
+    w = (w + w[::-1, :] + w[:, ::-1] + w[::-1, ::-1]) / 4.0
+    return synth.to_f32_exact(w / w.sum())
+
+
+SYM_CASES = [
+    ("star2d_m4", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (136, 2048), 12, 4, True),
+    ("star2d_m2", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (100, 1024), 9, 2, True),
+    ("star2d_plain", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (64, 512), 7, 1, True),
+    ("symbox_m3", _symmetric_box(), sf.STENCIL_BOX, (90, 768), 9, 3, True),
+    ("asym_box_m2", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (64, 512), 6, 2, False),
+    ("star2d_ragged_m4", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (77, 301), 8, 4, False),
+]
+
+
+@pytest.mark.parametrize("case", SYM_CASES, ids=lambda c: c[0])
+def test_symmetric_mode(case):
+    """Symmetric operators on vector-aligned grids: within 1e-5 of the FP64
+    oracle (the order differs from the canonical one); everything else falls
+    back to the canonical kernels and stays bit-exact."""
+    name, w, kind, shape, T, m, shared = case
+    w = synth.to_f32_exact(w)
+    u0 = synth.grid_f32(shape)
+    got = run_gpu(w, kind, u0, T, m, sf.STENCIL_MODE_SYMMETRIC)
+    ref64 = oracle.sweep(w, u0.astype(np.float64), T)
+    assert oracle.errors(got, ref64)["e_rel"] < 1e-5
+    mirror = oracle.folded_reference_f32(w, u0, T, m)
+    if not shared:
+        assert np.array_equal(got, mirror)
