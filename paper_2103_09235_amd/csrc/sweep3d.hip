@@ -230,6 +230,7 @@ hipError_t launch_one(const SweepLaunch &L, const std::vector<T> &w) {
   if (const char *e = std::getenv("STENCIL_TILE_Z")) bz = std::atoi(e);
   if (bz <= 0) {
     const int64_t xy = (int64_t)tiles_x * tiles_y;
+    // about 1024 workgroups (128-plane segments at 512^3) measured best
     const int64_t target_z = std::max<int64_t>(1, (1024 + xy - 1) / xy);
     bz = (int)((nz + target_z - 1) / target_z);
   }
