@@ -133,6 +133,18 @@ int stencil_fold_weights_f32(stencil_plan p, float *out, int64_t *out_len);
 int stencil_plan_set_mode(stencil_plan p, int mode);
 
 /*
+ * stencil_plan_set_fusion -- the most operator applications one launch may
+ * fuse (temporal blocking: Section 3.4 keeps several time steps of a tile on
+ * chip between loads).  The 1D kernels and the 2D FP32 VECTOR kernels
+ * (radius 1-4, rows of whole 16-byte vectors, at least 256 columns) fuse
+ * steps in registers; either way the result equals one launch per
+ * application bit for bit.  0 = the library's choice
+ * (default), 1 = one application per launch, k > 1 = at most k.
+ * Errors: E_ARG.  No device work.
+ */
+int stencil_plan_set_fusion(stencil_plan p, int max_steps);
+
+/*
  * stencil_plan_info -- read back plan parameters (any pointer may be NULL):
  * dimension, radius r, fold depth m, folded radius m*r, mode.
  */

@@ -30,8 +30,8 @@ STENCIL_E_STATE = -5
 # Symbols include/stencil.h declares.
 EXPORTS = (
     "stencil_plan_create", "stencil_fold_weights", "stencil_fold_weights_f32",
-    "stencil_plan_set_mode", "stencil_plan_info", "stencil_profitability",
-    "stencil_run", "stencil_run_batched", "stencil_residual",
+    "stencil_plan_set_mode", "stencil_plan_set_fusion", "stencil_plan_info",
+    "stencil_profitability", "stencil_run", "stencil_run_batched", "stencil_residual",
     "stencil_plan_destroy", "stencil_last_error", "stencil_version",
 )
 
@@ -84,6 +84,7 @@ def _load() -> ctypes.CDLL:
     lib.stencil_fold_weights.argtypes = [P, ctypes.c_int, dp, i64p]
     lib.stencil_fold_weights_f32.argtypes = [P, fp, i64p]
     lib.stencil_plan_set_mode.argtypes = [P, ctypes.c_int]
+    lib.stencil_plan_set_fusion.argtypes = [P, ctypes.c_int]
     lib.stencil_plan_info.argtypes = [P, ip, ip, ip, ip, ip]
     lib.stencil_profitability.argtypes = [P, ctypes.c_int, i64p, i64p]
     lib.stencil_run.argtypes = [P, ctypes.POINTER(stencil_grid), ctypes.c_int64]
@@ -148,6 +149,10 @@ def stencil_fold_weights_f32(plan) -> np.ndarray:
 
 def stencil_plan_set_mode(plan, mode: int) -> None:
     _check(lib.stencil_plan_set_mode(plan, mode))
+
+
+def stencil_plan_set_fusion(plan, max_steps: int) -> None:
+    _check(lib.stencil_plan_set_fusion(plan, max_steps))
 
 
 def stencil_plan_info(plan) -> dict:
@@ -257,6 +262,9 @@ class Plan:
 
     def set_mode(self, mode: int) -> None:
         stencil_plan_set_mode(self.handle, mode)
+
+    def set_fusion(self, max_steps: int) -> None:
+        stencil_plan_set_fusion(self.handle, max_steps)
 
     def info(self) -> dict:
         return stencil_plan_info(self.handle)

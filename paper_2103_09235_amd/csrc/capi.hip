@@ -156,7 +156,7 @@ hipError_t dispatch(stencil_plan p, const SweepLaunch &L) {
   else if (L.g.dim == 2) {
     SweepLaunch Ls = L;
     Ls.sym = p->mode == STENCIL_MODE_SYMMETRIC;
-    e = launch_sweep2d(Ls);
+    e = L.steps > 1 ? launch_sweep2d_tb(Ls) : launch_sweep2d(Ls);
   }
   else e = launch_sweep3d(L);
   if (e == hipErrorNotSupported) {
@@ -303,6 +303,14 @@ int stencil_plan_set_mode(stencil_plan p, int mode) {
   return STENCIL_OK;
 }
 
+int stencil_plan_set_fusion(stencil_plan p, int max_steps) {
+  set_error("");
+  if (int rc = check_plan(p)) return rc;
+  if (max_steps < 0) return fail(STENCIL_E_ARG, "max_steps must be >= 0");
+  p->max_fuse = max_steps;
+  return STENCIL_OK;
+}
+
 int stencil_plan_info(stencil_plan p, int *dim, int *radius, int *m,
                       int *folded_radius, int *mode) {
   set_error("");
@@ -396,7 +404,7 @@ int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
   const int64_t s = p->m > 1 ? T % p->m : T;
 
   // Work list: (operator, applications).  Tiled kernels may fuse several
-  // applications of one operator per launch (1D temporal blocking).
+  // applications of one operator per launch (1D and 2D temporal blocking).
   struct Pass { const OperatorDev *op; int64_t apps; };
   Pass passes[2] = {{folded, q}, {plain, s}};
   SweepLaunch L;
@@ -410,8 +418,11 @@ int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
   for (int i = 0; i < 2; ++i) {
     if (passes[i].apps == 0) continue;
     L.op = passes[i].op;
-    kmax[i] = (p->mode == STENCIL_MODE_EXACT_ORDER || p->dim != 1) ? 1
-              : std::max(1, sweep1d_max_steps(L));
+    if (p->dim == 1 && p->mode != STENCIL_MODE_EXACT_ORDER)
+      kmax[i] = std::max(1, sweep1d_max_steps(L));
+    else if (p->dim == 2 && p->mode == STENCIL_MODE_VECTOR)
+      kmax[i] = std::max(1, sweep2d_max_steps(L));
+    if (p->max_fuse > 0) kmax[i] = std::min<int64_t>(kmax[i], p->max_fuse);
     launches[i] = (passes[i].apps + kmax[i] - 1) / kmax[i];
   }
   for (int i = 0; i < 2; ++i) {

@@ -69,6 +69,7 @@ struct DeviceState {
 
 struct stencil_plan_s {
   int dim = 0, r = 0, shape = 0, boundary = 0, mode = STENCIL_MODE_VECTOR;
+  int max_fuse = 0;           // steps one launch may fuse; 0 = library choice
   std::vector<double> w;      // plain weights, FP64, (2r+1)^dim
   int m = 1;                  // fold depth
   std::vector<double> Wm;     // folded FP64 weights, (2mr+1)^dim
@@ -122,6 +123,10 @@ hipError_t launch_mfma2d(const SweepLaunch &L);
 std::vector<uint16_t> mfma_b_table(const std::vector<float> &w, int R);
 // Largest number of fused steps the 1D kernel takes per launch.
 int sweep1d_max_steps(const SweepLaunch &L);
+// 2D FP32 temporal blocking: the most steps one launch fuses (1 = none), and
+// the launch of 2 <= L.steps <= that many steps.
+int sweep2d_max_steps(const SweepLaunch &L);
+hipError_t launch_sweep2d_tb(const SweepLaunch &L);
 
 // FP64 fold convolution: out = a (radius Ra) * w (radius r), dim d.
 hipError_t launch_fold_conv(const double *a, int Ra, const double *w, int r,

@@ -1,0 +1,277 @@
+// 2D sweep with K time steps per pass over HBM (temporal blocking in
+// registers), bit-identical to K separate plain sweeps.
+//
+// The paper keeps several steps of a tile on chip with tessellate tiling
+// (Section 3.4) so data is not reloaded between steps.  Here a wavefront
+// streams a 256-column strip down y through a pipeline of K stages: stage s
+// turns rows of time level s into rows of level s+1 with the accumulator
+// queue of the single-step kernel (2R+1 pending rows in registers, four
+// columns per lane, the R columns beyond them fetched from the neighbouring
+// lanes by DPP) and hands each finished row straight to stage s+1.  Only
+// level 0 is read from HBM and only level K is written.
+//
+// Each level loses R valid columns at both ends of the strip (strips do not
+// exchange halos), so a strip loads 256 columns and stores the middle
+// 256 - 2B, B = K*R rounded up to a whole 16-byte vector; rows likewise: a
+// strip of BY output rows streams BY + 2KR input rows, and rows of a level
+// that lack history only ever feed rows of the next level that are not
+// stored.  Every stored value went through K plain steps in the canonical
+// order (acc = +0, one FMA per tap, offsets row-major), so the result equals
+// K plain sweeps bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+
+#include "internal.h"
+#include "sweep2d_impl.h"
+
+namespace stencil {
+
+namespace {
+
+using k2d::fmat;
+using k2d::in_mask;
+using k2d::load_vec;
+using k2d::store_vec;
+using k2d::WArr;
+using k2d::wrap1;
+
+constexpr int kVX = 4;
+constexpr int kSpan = 64 * kVX;  // columns a wavefront holds
+
+__host__ __device__ constexpr int border(int K, int R) { return (K * R + kVX - 1) / kVX * kVX; }
+
+// Whole-wavefront DPP shifts by one lane: lane i receives lane i-1's value
+// (shr) or lane i+1's (shl); the end lanes receive 0.
+__device__ __forceinline__ float lane_from_left(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
+                                                                0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float lane_from_right(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
+                                                                0x130, 0xF, 0xF, true));
+}
+
+template <int R, int MASK, int K>
+__global__ void __launch_bounds__(64)
+k_sweep2d_tb(const float *__restrict__ in, float *__restrict__ out, int ny, int nx, int BY,
+             int tiles_x, WArr<float, (2 * R + 1) * (2 * R + 1)> W) {
+  constexpr int S = 2 * R + 1;
+  constexpr int NU = S;                        // queue length = unroll of the row loop
+  constexpr int B = border(K, R);
+  constexpr int WOUT = kSpan - 2 * B;          // stored columns per strip
+  static_assert(WOUT > 0, "strip geometry");
+  static_assert(R <= kVX, "halo columns come from the two neighbouring lanes");
+
+  const int lane = threadIdx.x;
+  const int t = k2d::xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = t % tiles_x, ty = t / tiles_x;
+  const int xo0 = tx * WOUT;     // first stored column of the strip
+  const int xi0 = xo0 - B;       // first loaded column (a multiple of 4)
+  const int y0 = ty * BY, y1 = min(y0 + BY, ny);
+  const int jstart = y0 - K * R, jend = y1 + K * R;  // level-0 rows streamed
+  // The lane's four columns xi0 + 4*lane .. +3 wrap as a whole (nx % 4 == 0).
+  const int gx = wrap1(xi0 + kVX * lane, nx);
+  // Stored lanes: four columns inside [B, kSpan - B) and inside the grid.
+  const int lo = kVX * lane - B;
+  const bool store_ok = lo >= 0 && lo + kVX <= WOUT && xo0 + lo + kVX <= nx;
+
+  float acc[K][NU][kVX];
+#pragma unroll
+  for (int s = 0; s < K; ++s)
+#pragma unroll
+    for (int k = 0; k < NU; ++k)
+#pragma unroll
+      for (int v = 0; v < kVX; ++v) acc[s][k][v] = 0.0f;
+
+  // One level-0 row j through the K stages; u = (j - jstart) mod NU.
+  auto row = [&](const int j, const int u, const float (&in_row)[kVX]) {
+    float cur[kVX];
+#pragma unroll
+    for (int v = 0; v < kVX; ++v) cur[v] = in_row[v];
+    // Stage s takes level-s row j - s*R and finishes level-(s+1) row
+    // j - (s+1)*R; the slot of an output row is fixed by its index mod NU.
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      // the R columns on either side come from the neighbouring lanes
+      float win[kVX + 2 * R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) win[i] = lane_from_left(cur[kVX - R + i]);
+#pragma unroll
+      for (int v = 0; v < kVX; ++v) win[R + v] = cur[v];
+#pragma unroll
+      for (int i = 0; i < R; ++i) win[R + kVX + i] = lane_from_right(cur[i]);
+      // input row j feeds output rows j-R+k with vertical offset oy = R-k;
+      // for each output row the offsets arrive with oy ascending, and the
+      // first one (k = 2R) starts the sum from +0 in place of a cleared slot
+#pragma unroll
+      for (int k = S - 1; k >= 0; --k) {
+        const int slot = (u + k) % NU;
+        const int oy = R - k;
+#pragma unroll
+        for (int ox = -R; ox <= R; ++ox) {
+          if (in_mask<MASK, R>(oy, ox)) {
+            const float wt = W[(oy + R) * S + (ox + R)];
+            const bool first = k == S - 1 && ox == (MASK == MASK_BOX ? -R : 0);
+#pragma unroll
+            for (int v = 0; v < kVX; ++v)
+              acc[s][slot][v] = fmat(wt, win[R + v + ox], first ? 0.0f : acc[s][slot][v]);
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < kVX; ++v) cur[v] = acc[s][u % NU][v];
+    }
+    const int yd = j - K * R;  // level-K row just completed
+    if (store_ok && yd >= y0 && yd < y1) store_vec<float, kVX>(out + (size_t)yd * nx + xo0 + lo, cur);
+  };
+
+  // Level-0 rows arrive a group of NU rows ahead: a group's loads are issued
+  // before the previous group's K*NU stage updates, which cover their
+  // latency (one row per wavefront in flight does not).  Two buffers
+  // alternate, so no register with a load in flight is ever copied (a copy
+  // makes the compiler wait for every outstanding access), and the loads are
+  // unconditional for the same reason: rows past the end re-read the last.
+  auto fetch = [&](const int j0, float (&buf)[NU][kVX]) {
+#pragma unroll
+    for (int p = 0; p < NU; ++p)
+      load_vec<float, kVX>(in + (size_t)wrap1(min(j0 + p, jend - 1), ny) * nx + gx, buf[p]);
+  };
+  float bufA[NU][kVX], bufB[NU][kVX];
+  fetch(jstart, bufA);
+  // Pairs of NU-row groups: up to 2NU-1 rows past jend are computed and
+  // dropped.
+  for (int jb = jstart; jb < jend; jb += 2 * NU) {
+    fetch(jb + NU, bufB);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) row(jb + u, u, bufA[u]);
+    fetch(jb + 2 * NU, bufA);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) row(jb + NU + u, u, bufB[u]);
+  }
+}
+
+// Wavefront slots the device holds at once for a kernel (one wave per block).
+template <typename F>
+int resident_blocks(F kernel) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 256 * 8;
+  }
+  return std::max(1, cus * per_cu);
+}
+
+template <int R, int MASK, int K>
+hipError_t launch_one(const SweepLaunch &L) {
+  constexpr int S = 2 * R + 1;
+  constexpr int WOUT = kSpan - 2 * border(K, R);
+  WArr<float, S * S> W;
+  for (int i = 0; i < S * S; ++i) W.v[i] = L.op->w32[i];
+  const int ny = (int)L.g.ny, nx = (int)L.g.nx;
+  const int tiles_x = (nx + WOUT - 1) / WOUT;
+  static const int env_by = [] {
+    const char *e = std::getenv("STENCIL_TB_ROWS");
+    return e ? std::atoi(e) : 0;
+  }();
+  int by = env_by;
+  if (by <= 0) {
+    // One strip per resident wavefront slot, each as tall as that allows
+    // (a second round of strips measured slower than taller strips, whose
+    // 2KR redundant rows cost less); at least 4KR rows.
+    static const int slots = resident_blocks(k_sweep2d_tb<R, MASK, K>);
+    const int tiles_y = std::max(1, slots / tiles_x);
+    by = std::max((ny + tiles_y - 1) / tiles_y, 4 * K * R);
+  }
+  by = std::min(by, ny);
+  const int tiles_y = (ny + by - 1) / by;
+  const int64_t blocks = (int64_t)tiles_x * tiles_y;
+  if (blocks > (1LL << 31) - 1) return hipErrorNotSupported;
+  hipLaunchKernelGGL((k_sweep2d_tb<R, MASK, K>), dim3((unsigned)blocks), dim3(64), 0, L.stream,
+                     (const float *)L.in, (float *)L.out, ny, nx, by, tiles_x, W);
+  return hipGetLastError();
+}
+
+template <int R, int MASK>
+hipError_t launch_k(const SweepLaunch &L);
+
+#define TB_CASE(R, MASK, K) \
+  case K: return launch_one<R, MASK, K>(L);
+
+template <>
+hipError_t launch_k<1, MASK_BOX>(const SweepLaunch &L) {
+  switch (L.steps) { TB_CASE(1, MASK_BOX, 2) TB_CASE(1, MASK_BOX, 3) TB_CASE(1, MASK_BOX, 4)
+    TB_CASE(1, MASK_BOX, 5) TB_CASE(1, MASK_BOX, 6) TB_CASE(1, MASK_BOX, 7) TB_CASE(1, MASK_BOX, 8) }
+  return hipErrorNotSupported;
+}
+template <>
+hipError_t launch_k<1, MASK_DIAMOND>(const SweepLaunch &L) {
+  switch (L.steps) { TB_CASE(1, MASK_DIAMOND, 2) TB_CASE(1, MASK_DIAMOND, 3) TB_CASE(1, MASK_DIAMOND, 4)
+    TB_CASE(1, MASK_DIAMOND, 5) TB_CASE(1, MASK_DIAMOND, 6) TB_CASE(1, MASK_DIAMOND, 7)
+    TB_CASE(1, MASK_DIAMOND, 8) }
+  return hipErrorNotSupported;
+}
+template <>
+hipError_t launch_k<2, MASK_BOX>(const SweepLaunch &L) {
+  switch (L.steps) { TB_CASE(2, MASK_BOX, 2) TB_CASE(2, MASK_BOX, 3) TB_CASE(2, MASK_BOX, 4) }
+  return hipErrorNotSupported;
+}
+template <>
+hipError_t launch_k<2, MASK_DIAMOND>(const SweepLaunch &L) {
+  switch (L.steps) { TB_CASE(2, MASK_DIAMOND, 2) TB_CASE(2, MASK_DIAMOND, 3) TB_CASE(2, MASK_DIAMOND, 4) }
+  return hipErrorNotSupported;
+}
+template <>
+hipError_t launch_k<3, MASK_BOX>(const SweepLaunch &L) {
+  switch (L.steps) { TB_CASE(3, MASK_BOX, 2) }
+  return hipErrorNotSupported;
+}
+template <>
+hipError_t launch_k<3, MASK_DIAMOND>(const SweepLaunch &L) {
+  switch (L.steps) { TB_CASE(3, MASK_DIAMOND, 2) }
+  return hipErrorNotSupported;
+}
+template <>
+hipError_t launch_k<4, MASK_BOX>(const SweepLaunch &L) {
+  switch (L.steps) { TB_CASE(4, MASK_BOX, 2) }
+  return hipErrorNotSupported;
+}
+template <>
+hipError_t launch_k<4, MASK_DIAMOND>(const SweepLaunch &L) {
+  switch (L.steps) { TB_CASE(4, MASK_DIAMOND, 2) }
+  return hipErrorNotSupported;
+}
+#undef TB_CASE
+
+// Most steps per pass by radius: the queue (K*(2R+1)*4 registers) and two
+// groups of 2R+1 prefetched rows must leave room for two or more waves/SIMD.
+int tb_max(int R) { return R == 1 ? 8 : R == 2 ? 4 : R <= 4 ? 2 : 1; }
+
+}  // namespace
+
+int sweep2d_max_steps(const SweepLaunch &L) {
+  const int R = L.op->R;
+  const int K = tb_max(R);
+  if (K < 2 || L.dtype != STENCIL_F32 || L.g.dim != 2) return 1;
+  if (L.g.nx % kVX != 0 || L.g.nx < kSpan || L.g.ny < 2 * K * R + 1) return 1;
+  if (L.g.nx > (1 << 30) || L.g.ny > (1 << 30)) return 1;
+  return K;
+}
+
+hipError_t launch_sweep2d_tb(const SweepLaunch &L) {
+  if (L.steps < 2 || L.steps > sweep2d_max_steps(L)) return hipErrorNotSupported;
+  if ((uintptr_t)L.in % 16 != 0 || (uintptr_t)L.out % 16 != 0) return hipErrorNotSupported;
+  const bool box = L.op->mask == MASK_BOX;  // the diamond contains the axes
+  switch (L.op->R) {
+    case 1: return box ? launch_k<1, MASK_BOX>(L) : launch_k<1, MASK_DIAMOND>(L);
+    case 2: return box ? launch_k<2, MASK_BOX>(L) : launch_k<2, MASK_DIAMOND>(L);
+    case 3: return box ? launch_k<3, MASK_BOX>(L) : launch_k<3, MASK_DIAMOND>(L);
+    case 4: return box ? launch_k<4, MASK_BOX>(L) : launch_k<4, MASK_DIAMOND>(L);
+    default: return hipErrorNotSupported;
+  }
+}
+
+}  // namespace stencil

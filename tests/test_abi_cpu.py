@@ -91,6 +91,11 @@ def test_plan_info_mode_and_profitability():
     assert e.value.code == sf.STENCIL_E_UNSUPPORTED
     with pytest.raises(sf.StencilError):
         p.profitability(0)
+    p.set_fusion(0)
+    p.set_fusion(3)
+    with pytest.raises(sf.StencilError) as e:
+        p.set_fusion(-1)
+    assert e.value.code == sf.STENCIL_E_ARG
 
 
 def test_plan_f32_weights_start_unfolded():

@@ -350,3 +350,60 @@ def test_symmetric_mode(case):
     mirror = oracle.folded_reference_f32(w, u0, T, m)
     if not shared:
         assert np.array_equal(got, mirror)
+
+
+# ------------------------------------------------- 2D temporal blocking
+
+def _star_weights(r, offset):
+    return synth.to_f32_exact(synth.random_positive_weights(2, r, offset=offset,
+                                                            mask=synth.star_mask(2, r)))
+
+
+def _box_weights(r, offset):
+    return synth.to_f32_exact(synth.random_positive_weights(2, r, offset=offset))
+
+
+TB_CASES = [
+    # (name, weights, kind, shape, T, m, fusion): each launch fuses up to
+    # `fusion` steps (0 = library choice); shapes span several 256-column
+    # strips with a ragged last strip, and the minimum row count 2KR+1
+    ("star_r1_k8", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (200, 1000), 16, 1, 0),
+    ("star_r1_min_rows", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (17, 256), 8, 1, 8),
+    ("box_r1_k7", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (150, 772), 14, 1, 7),
+    ("box_r1_k5_k6", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (99, 516), 11, 1, 6),
+    ("star_r1_k3_k4", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (64, 260), 7, 1, 4),
+    ("star_r1_k2", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (40, 300), 4, 1, 2),
+    ("star_r2_plain", _star_weights(2, 100), sf.STENCIL_STAR, (120, 1024), 8, 1, 0),
+    ("box_r2_plain_k3", _box_weights(2, 200), sf.STENCIL_BOX, (80, 520), 9, 1, 3),
+    ("star2d_m2_fused", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (150, 768), 16, 2, 0),
+    ("box2d_m2_fused", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (64, 2048), 14, 2, 0),
+    ("star_r3_plain", _star_weights(3, 300), sf.STENCIL_STAR, (90, 512), 6, 1, 0),
+    ("box2d_m3_fused", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (61, 764), 15, 3, 0),
+    ("star2d_m4_fused", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (300, 1024), 16, 4, 0),
+    ("box_r4_plain", _box_weights(4, 400), sf.STENCIL_BOX, (17, 256), 4, 1, 0),
+]
+
+
+@pytest.mark.parametrize("case", TB_CASES, ids=lambda c: c[0])
+def test_temporal_blocking_bit_exact(case):
+    """Several steps per launch (registers + LDS) equal one launch per step
+    bit for bit: compared with the oracle's FP32 mirror of the schedule and
+    with the same plan run unfused."""
+    name, w, kind, shape, T, m, fusion = case
+    w = synth.to_f32_exact(w)
+    u0 = synth.grid_f32(shape)
+    print("temporal blocking", name, shape, "T", T, "m", m, "fusion", fusion, flush=True)
+    outs = []
+    for fz in (fusion, 1):
+        plan = sf.Plan(w, kind)
+        if m > 1:
+            plan.fold(m)
+        plan.set_fusion(fz)
+        data = torch.from_numpy(u0).to(DEV)
+        plan.run(data, T, torch.empty_like(data))
+        torch.cuda.synchronize()
+        outs.append(data.cpu().numpy())
+        plan.close()
+    ref = oracle.folded_reference_f32(w, u0, T, m)
+    assert np.array_equal(outs[0], ref)
+    assert np.array_equal(outs[1], ref)
