@@ -7,8 +7,11 @@ Default workload: the 2D 5-point star (centre 0.6, neighbours 0.1, FP32
 weights), 8192 x 8192 FP32 periodic grid, T = 1000 original steps, uniform
 [0, 1) initial values (SplitMix64, seed 2103).  One step = one stencil_run of
 all T steps (plan and folded weights prepared beforehand, grid resident in
-HBM).  The headline form is the fold depth m = 4 (41-point folded operator);
-the plain sweep and m = 2 are timed beside it under "forms".
+HBM).  Forms: the plain sweep and the folds m = 2 and m = 4 (13- and 41-point
+folded operators), each as one launch per application ("vector_unfused"),
+with several applications fused per launch ("vector", temporal blocking),
+and with mirrored partial sums shared ("symmetric"); the fastest form of a
+stated fold depth is the headline, all of them are listed under "forms".
 
 Other workloads (--workload): heat1d, star3d, box3d, box2d, batched.
 
@@ -30,7 +33,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-FP32_VECTOR_TFLOPS = 157.3      # MI355X FP32 vector, published
+FP32_VECTOR_TFLOPS = 157.3      # MI355X FP32 vector, published (packed FP32 FMAs)
+# FP32 FMA issue rate without packed FP32 (the kernels are built with packed
+# FP32 disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+FP32_FMA_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+FP32_FMA_BASIS = ("FP32 FMA issue rate without packed FP32: 256 CUs x 64 lanes x 2 flop x "
+                  "2.4 GHz = 78.6 TFLOP/s (the published 157.3 counts packed FP32 FMAs, "
+                  "which these kernels do not use)")
 FP64_VECTOR_TFLOPS = 78.6       # MI355X FP64 vector, published
 BF16_MFMA_TFLOPS = 2500.0       # MI355X dense BF16 matrix, published
 METRIC = "GStencil/s and % HBM roofline, plain vs folded/MFMA/batched at stated error"
@@ -51,7 +60,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only-m", type=int, default=0,
                     help="time only this fold depth (profiling runs)")
-    ap.add_argument("--only-mode", default="", choices=["", "vector", "symmetric", "mfma_bf16x3"],
+    ap.add_argument("--only-mode", default="",
+                    choices=["", "vector", "vector_unfused", "symmetric", "mfma_bf16x3"],
                     help="time only this kernel family (profiling runs)")
     ap.add_argument("--no-per-grid", action="store_true",
                     help="batched: skip the per-grid-launch baseline (profiling runs)")
@@ -60,27 +70,44 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash() -> str:
+# Source files each kernel family is built from (plus internal.h): a
+# committed PMC summary stays valid while these are unchanged.
+KERNEL_SOURCES = {
+    "sweep1d": ("sweep1d.hip",),
+    "sweep2d": ("sweep2d.hip", "sweep2d_impl.h", "sweep2d_launch.h", "sweep2d_r1.hip",
+                "sweep2d_r2.hip", "sweep2d_r3.hip", "sweep2d_r4.hip", "sweep2d_r5.hip",
+                "sweep2d_r6.hip", "sweep2d_r7.hip", "sweep2d_r8.hip"),
+    "sweep2dtb": ("sweep2d_tb.hip", "sweep2d_impl.h"),
+    "sweep3d": ("sweep3d.hip",),
+    "mfma2d": ("mfma2d.hip",),
+    "batched": ("batched.hip", "sweep2d_impl.h"),
+}
+
+
+def kernel_family(kernel_key: str) -> str:
+    return kernel_key.split("_")[0]
+
+
+def kernel_source_hash(family: str) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2103_09235_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in ("internal.h",) + KERNEL_SOURCES[family]:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def traffic_from_profiles(kernel_key: str, workload: str):
     """HBM bytes per launch from a committed rocprofv3 PMC summary, if one
-    exists for this kernel and workload and the kernel sources have not
+    exists for this kernel and workload and the kernel's sources have not
     changed since it was taken (its 'source-hash' line)."""
     path = os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (kernel_key, workload))
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"source-hash:\s*(\w+)", text)
-    if not m or m.group(1) != kernel_source_hash():
+    if not m or m.group(1) != kernel_source_hash(kernel_family(kernel_key)):
         return None
     b = re.search(r"hbm-bytes-per-launch:\s*([0-9.eE+]+)", text)
     return float(b.group(1)) if b else None
@@ -173,7 +200,6 @@ def bench_grid(args, wl_name):
 
     forms = {}
     ref64 = None
-    modes = [("vector", sf.STENCIL_MODE_VECTOR)]
     headline = None
     symmetric = wl.dim == 2 and np.array_equal(w, w[::-1, :]) and np.array_equal(w, w[:, ::-1])
     # extra fold depths beyond the workload's stated ones are reported under
@@ -182,12 +208,19 @@ def bench_grid(args, wl_name):
     for m in tuple(wl.folds) + extra:
         if args.only_m and m != args.only_m:
             continue
-        form_modes = list(modes) if m not in extra else []
+        # (name, mode, fusion): VECTOR fuses several applications per launch
+        # where the tiled kernel can (2D FP32 radius <= 4, 1D); "unfused" is
+        # the same kernel family one application per launch
+        form_modes = []
+        if m not in extra:
+            form_modes.append(("vector", sf.STENCIL_MODE_VECTOR, 0))
+            if wl.dim == 2 and f32:
+                form_modes.append(("vector_unfused", sf.STENCIL_MODE_VECTOR, 1))
         if symmetric:
-            form_modes.append(("symmetric", sf.STENCIL_MODE_SYMMETRIC))
+            form_modes.append(("symmetric", sf.STENCIL_MODE_SYMMETRIC, 0))
         if wl_name == "box2d" and m > 1:
-            form_modes.append(("mfma_bf16x3", sf.STENCIL_MODE_MFMA_BF16X3))
-        for mode_name, mode in form_modes:
+            form_modes.append(("mfma_bf16x3", sf.STENCIL_MODE_MFMA_BF16X3, 0))
+        for mode_name, mode, fusion in form_modes:
             if args.only_mode and mode_name != args.only_mode:
                 continue
             plan = sf.Plan(w, wl.shape_kind)
@@ -198,7 +231,9 @@ def bench_grid(args, wl_name):
             except sf.StencilError as e:
                 log("[bench] skip m=%d %s: %s" % (m, mode_name, e))
                 continue
+            plan.set_fusion(fusion)
             data.copy_(torch.from_numpy(u0).to(dev))
+            sched = plan.schedule(data, T, scratch)
 
             def step():
                 plan.run(data, T, scratch)
@@ -209,8 +244,6 @@ def bench_grid(args, wl_name):
             except sf.StencilError as e:
                 log("[bench] skip m=%d %s: %s" % (m, mode_name, e))
                 continue
-            q, r = divmod(T, m) if m > 1 else (0, T)
-            sweeps = q + r
             # mass after the timed runs: data has advanced (warmup+steps)*T steps
             total_T = (args.warmup + args.steps) * T
             s1, _, _ = sf.stencil_residual(data)
@@ -224,52 +257,69 @@ def bench_grid(args, wl_name):
                 ref64 = fp64_reference(sf, w, wl.shape_kind, u0, T)
             err, err_detr = error_vs(ref64, data)
             gst = n * T * args.steps / el / 1e9
-            sweep_ms = el / args.steps / sweeps * 1e3
+            launches = sched["folded_launches"] + sched["plain_launches"]
+            # the dominant kernel: the folded pass when there is one
+            dom = "folded" if sched["folded_launches"] else "plain"
+            per_launch = sched[dom + "_apps"] / sched[dom + "_launches"]
+            launch_ms = el / args.steps / launches * 1e3
             algo_bytes = 2 * esz * n
             taps = int(np.count_nonzero(plan.fold(m) if m > 1 else w))
-            flops = 2 * taps * n
+            flops = 2 * taps * n * per_launch
             key = "%s_m%d_%s" % (wl_name, m, mode_name)
             forms[key] = {
                 "m": m, "mode": mode_name, "gstencil_s": round(gst, 2),
                 "ms_per_run": round(el / args.steps * 1e3, 4),
-                "ms_per_sweep": round(sweep_ms, 5),
-                "sweep_launches_per_run": sweeps, "taps": taps,
-                "hbm_gbs_algorithmic": round(algo_bytes / (sweep_ms / 1e3) / 1e9, 1),
-                "hbm_frac": round(algo_bytes / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "launches_per_run": launches,
+                "applications_per_launch": round(per_launch, 3),
+                "ms_per_launch": round(launch_ms, 5), "taps": taps,
+                "hbm_gbs_algorithmic": round(algo_bytes / (launch_ms / 1e3) / 1e9, 1),
+                "hbm_frac": round(algo_bytes / (launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "alu_tflops": round(flops / (launch_ms / 1e3) / 1e12, 2),
                 "e_rel_vs_fp64": err, "e_detrended_vs_fp64": err_detr,
                 "mass_rel_drift": mass_rel, "mass_T": total_T,
                 "wall_s": round(wall, 3),
             }
-            log("[bench]   %.1f GStencil/s, %.4f ms/sweep, e_rel %.2e (detrended %.2e), "
-                "mass drift %.2e" % (gst, sweep_ms, err, err_detr, mass_rel))
+            log("[bench]   %.1f GStencil/s, %d launches of %.2f applications, %.4f ms/launch, "
+                "e_rel %.2e (detrended %.2e), mass drift %.2e" % (
+                    gst, launches, per_launch, launch_ms, err, err_detr, mass_rel))
             forms[key]["stated_fold"] = m not in extra
             if m not in extra and (headline is None or gst > headline[1]):
-                headline = (key, gst, el, sweep_ms, algo_bytes, flops, m, mode_name, taps)
+                headline = (key, gst, el, launch_ms, algo_bytes, flops, m, mode_name, taps,
+                            per_launch)
             plan.close()
-    key, gst, el, sweep_ms, algo_bytes, flops, m, mode_name, taps = headline
+    key, gst, el, launch_ms, algo_bytes, flops, m, mode_name, taps, per_launch = headline
     intensity = flops / algo_bytes
     if mode_name.startswith("mfma"):
-        peak_t = BF16_MFMA_TFLOPS
+        peak_t, basis = BF16_MFMA_TFLOPS, "dense BF16 matrix, published"
+    elif f32:
+        peak_t, basis = FP32_FMA_TFLOPS, FP32_FMA_BASIS
     else:
-        peak_t = FP32_VECTOR_TFLOPS if f32 else FP64_VECTOR_TFLOPS
+        peak_t, basis = FP64_VECTOR_TFLOPS, "FP64 vector, published"
     ridge = peak_t * 1e12 / (HBM_PEAK_GBS * 1e9)
-    dur = sweep_ms / 1e3
+    dur = launch_ms / 1e3
     if intensity < ridge or mode_name.startswith("mfma"):
         roof = {"bound": "hbm", "achieved": round(algo_bytes / dur / 1e9, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     else:
         roof = {"bound": "alu", "achieved": round(flops / dur / 1e12, 2),
-                "peak": peak_t, "unit": "TFLOP/s"}
+                "peak": peak_t, "unit": "TFLOP/s", "peak_basis": basis}
+        if f32:
+            roof["frac_of_published_fp32_vector"] = round(roof["achieved"] / FP32_VECTOR_TFLOPS, 4)
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    tkey = {"vector": "sweep%dd_m%d" % (wl.dim, m),
+    fused = per_launch > 1 and wl.dim == 2
+    tkey = {"vector": ("sweep%dd%s_m%d" % (wl.dim, "tb" if fused else "", m)),
+            "vector_unfused": "sweep%dd_m%d" % (wl.dim, m),
             "symmetric": "sweep%dd_m%d_symmetric" % (wl.dim, m),
             "mfma_bf16x3": "mfma2d_m%d" % m}[mode_name]
     roof["traffic"] = traffic_from_profiles(tkey, wl_name)
-    roof["kernel"] = "k_sweep%dd R=%d (%s, %d taps)" % (wl.dim, m * ((w.shape[0] - 1) // 2),
-                                                        mode_name, taps)
-    roof["launch_ms"] = round(sweep_ms, 5)
+    roof["kernel"] = "%s R=%d (%s, %d taps, %.2f applications per launch)" % (
+        "k_sweep2d_tb" if fused else ("k_mfma2d" if mode_name.startswith("mfma")
+                                      else "k_sweep%dd" % wl.dim),
+        m * ((w.shape[0] - 1) // 2), mode_name, taps, per_launch)
+    roof["launch_ms"] = round(launch_ms, 5)
     roof["algorithmic_bytes_per_launch"] = algo_bytes
     roof["algorithmic_flops_per_launch"] = flops
+    roof["hbm_frac"] = round(algo_bytes / dur / 1e9 / HBM_PEAK_GBS, 4)
     res = {
         "metric": METRIC,
         "value": round(gst, 2),

@@ -181,6 +181,20 @@ int stencil_profitability(stencil_plan p, int m, int64_t *naive,
 int stencil_run(stencil_plan p, stencil_grid *g, int64_t T);
 
 /*
+ * stencil_run_schedule -- the launches stencil_run(p, g, T) would enqueue,
+ * with no device work: out[0] applications of W_m in out[1] launches, then
+ * out[2] applications of the plain weights in out[3] launches (a launch
+ * fuses one or more applications; see stencil_plan_set_fusion), and
+ * *final_copy (nullable) = 1 if the run ends with the device copy back into
+ * g->data.  Takes the same arguments and returns the same argument errors as
+ * stencil_run (the pointers are only compared, never dereferenced).
+ *   out  host, 4 int64_t.
+ * Errors: E_ARG, E_UNSUPPORTED.
+ */
+int stencil_run_schedule(stencil_plan p, const stencil_grid *g, int64_t T,
+                         int64_t *out, int *final_copy);
+
+/*
  * stencil_run_batched -- advance count independent 2D grids by T steps each,
  * grids[i] with plans[i] (plans may repeat; every plan must be 2D), with one
  * persistent launch per (folded) sweep over all grids together and, when

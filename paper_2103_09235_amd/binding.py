@@ -31,7 +31,7 @@ STENCIL_E_STATE = -5
 EXPORTS = (
     "stencil_plan_create", "stencil_fold_weights", "stencil_fold_weights_f32",
     "stencil_plan_set_mode", "stencil_plan_set_fusion", "stencil_plan_info",
-    "stencil_profitability", "stencil_run", "stencil_run_batched", "stencil_residual",
+    "stencil_profitability", "stencil_run", "stencil_run_schedule", "stencil_run_batched", "stencil_residual",
     "stencil_plan_destroy", "stencil_last_error", "stencil_version",
 )
 
@@ -88,6 +88,7 @@ def _load() -> ctypes.CDLL:
     lib.stencil_plan_info.argtypes = [P, ip, ip, ip, ip, ip]
     lib.stencil_profitability.argtypes = [P, ctypes.c_int, i64p, i64p]
     lib.stencil_run.argtypes = [P, ctypes.POINTER(stencil_grid), ctypes.c_int64]
+    lib.stencil_run_schedule.argtypes = [P, ctypes.POINTER(stencil_grid), ctypes.c_int64, i64p, ip]
     lib.stencil_run_batched.argtypes = [ctypes.POINTER(P), ctypes.POINTER(stencil_grid),
                                         ctypes.c_int, ctypes.c_int64,
                                         ctypes.POINTER(stencil_batch_opts)]
@@ -202,6 +203,26 @@ def stencil_run(plan, data, T: int, scratch=None, stream=None) -> None:
     _check(lib.stencil_run(plan, ctypes.byref(g), int(T)))
 
 
+def stencil_run_schedule(plan, shape, dtype: int, T: int, data_ptr: int,
+                         scratch_ptr: int | None = None) -> dict:
+    """Launch plan of a run on a grid of this shape and dtype whose buffers
+    sit at these device addresses (compared only, never dereferenced)."""
+    g = stencil_grid()
+    g.data = data_ptr
+    g.scratch = scratch_ptr
+    g.dtype = dtype
+    g.dim = len(shape)
+    for i, n in enumerate(shape):
+        g.shape[i] = int(n)
+    out = (ctypes.c_int64 * 4)()
+    copy = ctypes.c_int()
+    _check(lib.stencil_run_schedule(plan, ctypes.byref(g), int(T),
+                                    ctypes.cast(out, ctypes.POINTER(ctypes.c_int64)),
+                                    ctypes.byref(copy)))
+    return {"folded_apps": out[0], "folded_launches": out[1], "plain_apps": out[2],
+            "plain_launches": out[3], "final_copy": bool(copy.value)}
+
+
 def stencil_run_batched(plans, datas, scratches, T: int, autotune: bool = False,
                         tune_cache: str | None = None, use_graph: bool = True,
                         max_m: int = 1, stream=None):
@@ -274,6 +295,12 @@ class Plan:
 
     def run(self, data, T: int, scratch=None, stream=None) -> None:
         stencil_run(self.handle, data, T, scratch, stream)
+
+    def schedule(self, data, T: int, scratch=None) -> dict:
+        """stencil_run_schedule for a device tensor (and scratch tensor)."""
+        return stencil_run_schedule(self.handle, tuple(data.shape), _dtype_code(data), T,
+                                    data.data_ptr(),
+                                    scratch.data_ptr() if scratch is not None else None)
 
     def close(self) -> None:
         if self.handle is not None:

@@ -337,8 +337,11 @@ int stencil_profitability(stencil_plan p, int m, int64_t *naive, int64_t *folded
   return STENCIL_OK;
 }
 
-int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
-  set_error("");
+namespace stencil {
+namespace {
+
+// Checks a run's arguments (no device work) and fills its geometry.
+int check_run(stencil_plan p, const stencil_grid *g, int64_t T, Geom &geo) {
   if (int rc = check_plan(p)) return rc;
   if (!g) return fail(STENCIL_E_ARG, "grid is NULL");
   if (T < 0) return fail(STENCIL_E_ARG, "T must be >= 0");
@@ -350,7 +353,7 @@ int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
     return fail(STENCIL_E_UNSUPPORTED, "MFMA mode takes FP32 grids only");
   if (p->mode == STENCIL_MODE_MFMA_BF16X3 && p->m * p->r > 8)
     return fail(STENCIL_E_UNSUPPORTED, "MFMA mode needs a folded radius m*r <= 8");
-  Geom geo;
+  geo = Geom();
   geo.dim = p->dim;
   int64_t n[3] = {1, 1, 1};
   for (int a = 0; a < p->dim; ++a) {
@@ -372,6 +375,76 @@ int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
     if (a < b + bytes && b < a + bytes)
       return fail(STENCIL_E_ARG, "data and scratch overlap");
   }
+  return STENCIL_OK;
+}
+
+// The launches of a run: floor(T/m) applications of the folded operator,
+// then T mod m of the plain one.  Tiled kernels may fuse several
+// applications of one operator per launch (1D and 2D temporal blocking);
+// the 2D fused kernel needs 16-byte aligned buffers (a plan-owned scratch
+// buffer always is).  An odd launch total leaves the result in scratch and
+// costs a final copy, unless a fusing pass can split once more.
+struct Schedule {
+  int64_t apps[2] = {0, 0};      // folded, plain
+  int64_t launches[2] = {0, 0};
+  bool final_copy = false;
+};
+
+Schedule make_schedule(stencil_plan p, const Geom &geo, int dtype, const void *data,
+                       const void *scratch, int64_t T) {
+  Schedule sc;
+  sc.apps[0] = p->m > 1 ? T / p->m : 0;
+  sc.apps[1] = p->m > 1 ? T % p->m : T;
+  const bool aligned = (uintptr_t)data % 16 == 0 && (uintptr_t)scratch % 16 == 0;
+  int64_t kmax[2] = {1, 1};
+  for (int i = 0; i < 2; ++i) {
+    if (sc.apps[i] == 0) continue;
+    OperatorDev op;
+    op.R = i == 0 ? p->m * p->r : p->r;
+    op.mask = mask_for(p->shape, i == 0 ? p->m : 1);
+    SweepLaunch L;
+    L.g = geo;
+    L.dtype = dtype;
+    L.op = &op;
+    if (p->dim == 1 && p->mode != STENCIL_MODE_EXACT_ORDER)
+      kmax[i] = std::max(1, sweep1d_max_steps(L));
+    else if (p->dim == 2 && p->mode == STENCIL_MODE_VECTOR && aligned)
+      kmax[i] = std::max(1, sweep2d_max_steps(L));
+    if (p->max_fuse > 0) kmax[i] = std::min<int64_t>(kmax[i], p->max_fuse);
+    sc.launches[i] = (sc.apps[i] + kmax[i] - 1) / kmax[i];
+  }
+  for (int i = 0; i < 2; ++i) {
+    if ((sc.launches[0] + sc.launches[1]) % 2 == 0) break;
+    if (kmax[i] > 1 && sc.launches[i] < sc.apps[i]) sc.launches[i] += 1;
+  }
+  sc.final_copy = (sc.launches[0] + sc.launches[1]) % 2 == 1;
+  return sc;
+}
+
+}  // namespace
+}  // namespace stencil
+
+int stencil_run_schedule(stencil_plan p, const stencil_grid *g, int64_t T, int64_t *out,
+                         int *final_copy) {
+  set_error("");
+  Geom geo;
+  if (int rc = check_run(p, g, T, geo)) return rc;
+  if (!out) return fail(STENCIL_E_ARG, "out is NULL");
+  // a plan-owned scratch buffer comes from hipMalloc (256-byte aligned)
+  const Schedule sc = make_schedule(p, geo, g->dtype, g->data, g->scratch, T);
+  out[0] = sc.apps[0];
+  out[1] = sc.launches[0];
+  out[2] = sc.apps[1];
+  out[3] = sc.launches[1];
+  if (final_copy) *final_copy = sc.final_copy ? 1 : 0;
+  return STENCIL_OK;
+}
+
+int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
+  set_error("");
+  Geom geo;
+  if (int rc = check_run(p, g, T, geo)) return rc;
+  const size_t bytes = (size_t)geo.count() * esize(g->dtype);
   if (T == 0) return STENCIL_OK;
 
   int device = 0;
@@ -398,45 +471,22 @@ int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
     }
     scratch = d.scratch;
   }
-  const OperatorDev *plain = g->dtype == STENCIL_F32 ? &d.plain32 : &d.plain64;
-  const OperatorDev *folded = g->dtype == STENCIL_F32 ? &d.fold32 : &d.fold64;
-  const int64_t q = p->m > 1 ? T / p->m : 0;
-  const int64_t s = p->m > 1 ? T % p->m : T;
-
-  // Work list: (operator, applications).  Tiled kernels may fuse several
-  // applications of one operator per launch (1D and 2D temporal blocking).
-  struct Pass { const OperatorDev *op; int64_t apps; };
-  Pass passes[2] = {{folded, q}, {plain, s}};
+  const OperatorDev *ops[2] = {g->dtype == STENCIL_F32 ? &d.fold32 : &d.fold64,
+                               g->dtype == STENCIL_F32 ? &d.plain32 : &d.plain64};
+  const Schedule sc = make_schedule(p, geo, g->dtype, g->data, scratch, T);
   SweepLaunch L;
   L.g = geo;
   L.dtype = g->dtype;
   L.stream = (hipStream_t)g->stream;
-  // Launch counts per pass, then parity: an odd total leaves the result in
-  // scratch and costs a final copy, unless a fusing pass can split once more.
-  int64_t launches[2] = {0, 0};
-  int64_t kmax[2] = {1, 1};
-  for (int i = 0; i < 2; ++i) {
-    if (passes[i].apps == 0) continue;
-    L.op = passes[i].op;
-    if (p->dim == 1 && p->mode != STENCIL_MODE_EXACT_ORDER)
-      kmax[i] = std::max(1, sweep1d_max_steps(L));
-    else if (p->dim == 2 && p->mode == STENCIL_MODE_VECTOR)
-      kmax[i] = std::max(1, sweep2d_max_steps(L));
-    if (p->max_fuse > 0) kmax[i] = std::min<int64_t>(kmax[i], p->max_fuse);
-    launches[i] = (passes[i].apps + kmax[i] - 1) / kmax[i];
-  }
-  for (int i = 0; i < 2; ++i) {
-    if ((launches[0] + launches[1]) % 2 == 0) break;
-    if (kmax[i] > 1 && launches[i] < passes[i].apps) launches[i] += 1;
-  }
   const void *src = g->data;
   void *dst = scratch;
   for (int i = 0; i < 2; ++i) {
-    if (passes[i].apps == 0) continue;
-    L.op = passes[i].op;
-    int64_t left = passes[i].apps;
-    for (int64_t k = 0; k < launches[i]; ++k) {
-      const int64_t take = (left + (launches[i] - k) - 1) / (launches[i] - k);
+    if (sc.apps[i] == 0) continue;
+    L.op = ops[i];
+    int64_t left = sc.apps[i];
+    const int64_t nl = sc.launches[i];
+    for (int64_t k = 0; k < nl; ++k) {
+      const int64_t take = (left + (nl - k) - 1) / (nl - k);
       L.in = src;
       L.out = dst;
       L.steps = (int)take;

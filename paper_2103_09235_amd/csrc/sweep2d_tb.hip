@@ -42,6 +42,14 @@ constexpr int kSpan = 64 * kVX;  // columns a wavefront holds
 
 __host__ __device__ constexpr int border(int K, int R) { return (K * R + kVX - 1) / kVX * kVX; }
 
+// Blocks are dealt round-robin to the 8 XCDs (block b to XCD b mod 8):
+// renumber them so each XCD runs one contiguous range of strips, for any
+// block count, and neighbouring strips share halo lines in one L2.
+__device__ __forceinline__ int xcd_contiguous(int b, int nb) {
+  const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+  return x * q + min(x, r) + i;
+}
+
 // Whole-wavefront DPP shifts by one lane: lane i receives lane i-1's value
 // (shr) or lane i+1's (shl); the end lanes receive 0.
 __device__ __forceinline__ float lane_from_left(float x) {
@@ -65,7 +73,7 @@ k_sweep2d_tb(const float *__restrict__ in, float *__restrict__ out, int ny, int 
   static_assert(R <= kVX, "halo columns come from the two neighbouring lanes");
 
   const int lane = threadIdx.x;
-  const int t = k2d::xcd_tile(blockIdx.x, gridDim.x);
+  const int t = xcd_contiguous(blockIdx.x, gridDim.x);
   const int tx = t % tiles_x, ty = t / tiles_x;
   const int xo0 = tx * WOUT;     // first stored column of the strip
   const int xi0 = xo0 - B;       // first loaded column (a multiple of 4)

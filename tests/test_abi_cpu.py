@@ -155,3 +155,55 @@ def test_batched_validation():
     g[0].data = None
     assert sf.lib.stencil_run_batched(parr, g, 1, 1, None) == sf.STENCIL_E_ARG
     assert sf.lib.stencil_run_batched(parr, g, 1, -1, None) == sf.STENCIL_E_ARG
+
+
+def _sched(plan, shape, T, dtype=None, data=1 << 20, scratch=None):
+    dtype = sf.STENCIL_F32 if dtype is None else dtype
+    return sf.stencil_run_schedule(plan.handle, shape, dtype, T, data, scratch)
+
+
+def test_run_schedule_counts_launches():
+    """Host-only launch plan: floor(T/m) folded then T mod m plain
+    applications, fused up to the kernel's depth, an even launch count
+    whenever a fusing pass can split once more, else a final copy."""
+    star = sf.Plan(synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR)
+    # 2D FP32 radius 1: up to 8 steps per launch; 1000 steps -> 125 -> 126
+    s = _sched(star, (8192, 8192), 1000)
+    assert (s["plain_apps"], s["plain_launches"], s["final_copy"]) == (1000, 126, False)
+    # T = 8 would be one launch: split in two so no copy is needed
+    assert _sched(star, (8192, 8192), 8)["plain_launches"] == 2
+    # T = 1 cannot split: one launch and a copy
+    s = _sched(star, (8192, 8192), 1)
+    assert (s["plain_launches"], s["final_copy"]) == (1, True)
+    # rows that are not whole 16-byte vectors, narrow grids, FP64, unaligned
+    # buffers: one step per launch
+    assert _sched(star, (8192, 8191), 10)["plain_launches"] == 10
+    assert _sched(star, (64, 252), 10)["plain_launches"] == 10
+    assert _sched(star, (512, 512), 10, sf.STENCIL_F64)["plain_launches"] == 10
+    assert _sched(star, (512, 512), 10, data=(1 << 20) + 4)["plain_launches"] == 10
+    assert _sched(star, (512, 512), 10, scratch=(1 << 30) + 8)["plain_launches"] == 10
+    # the fusion cap
+    star.set_fusion(1)
+    assert _sched(star, (8192, 8192), 16)["plain_launches"] == 16
+    star.set_fusion(3)
+    assert _sched(star, (8192, 8192), 16)["plain_launches"] == 6
+    star.set_fusion(0)
+    # radius 4: up to 2 per launch (folded plans: the GPU tests)
+    w4 = synth.random_positive_weights(2, 4, mask=synth.star_mask(2, 4))
+    s = _sched(sf.Plan(w4, sf.STENCIL_STAR), (8192, 8192), 1001)
+    assert (s["plain_launches"], s["final_copy"]) == (502, False)
+    # modes other than VECTOR run one application per launch in 2D
+    star.set_mode(sf.STENCIL_MODE_SYMMETRIC)
+    assert _sched(star, (8192, 8192), 1000)["plain_launches"] == 1000
+    # 1D fuses many steps per launch; 3D none
+    heat = sf.Plan(synth.heat1d_weights(), sf.STENCIL_STAR)
+    assert _sched(heat, (1_000_000,), 100, sf.STENCIL_F64)["plain_launches"] < 10
+    box3 = sf.Plan(np.ones((3, 3, 3)) / 27, sf.STENCIL_BOX)
+    s = _sched(box3, (64, 64, 64), 5)
+    assert (s["plain_launches"], s["final_copy"]) == (5, True)
+    with pytest.raises(sf.StencilError) as e:
+        _sched(star, (8192, 8192), -1)
+    assert e.value.code == sf.STENCIL_E_ARG
+    with pytest.raises(sf.StencilError) as e:
+        _sched(star, (2, 8192), 4)
+    assert e.value.code == sf.STENCIL_E_UNSUPPORTED

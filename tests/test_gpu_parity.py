@@ -407,3 +407,23 @@ def test_temporal_blocking_bit_exact(case):
     ref = oracle.folded_reference_f32(w, u0, T, m)
     assert np.array_equal(outs[0], ref)
     assert np.array_equal(outs[1], ref)
+
+
+def test_run_schedule_folded_then_plain():
+    """floor(T/m) applications of W_m (radius 4: two per launch), then the
+    T mod m plain ones; the reported plan is the one stencil_run follows
+    (same result as the oracle's mirror of the schedule)."""
+    w = synth.WORKLOADS["star2d"].weights
+    plan = sf.Plan(w, sf.STENCIL_STAR)
+    plan.fold(4)
+    u0 = synth.grid_f32((40, 512))
+    data = torch.from_numpy(u0).to(DEV)
+    scr = torch.empty_like(data)
+    s = plan.schedule(data, 17, scr)
+    # 2 + 1 launches would end in scratch: the folded pass splits once more
+    assert (s["folded_apps"], s["folded_launches"], s["plain_apps"]) == (4, 3, 1)
+    assert s["plain_launches"] == 1 and not s["final_copy"]
+    plan.run(data, 17, scr)
+    torch.cuda.synchronize()
+    assert np.array_equal(data.cpu().numpy(), oracle.folded_reference_f32(w, u0, 17, 4))
+    plan.close()
