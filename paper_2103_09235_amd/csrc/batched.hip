@@ -187,6 +187,9 @@ int tune_one(stencil_plan p, int side, int max_m, hipStream_t stream, int *best_
     stencil_plan_s tmp = *p;  // same weights, own fold depth and device state
     tmp.dev.clear();
     tmp.batch_w32.clear();
+    // the batched kernel applies the operator once per launch: time that
+    tmp.mode = STENCIL_MODE_VECTOR;
+    tmp.max_fuse = 1;
     rc = stencil_fold_weights(&tmp, m, nullptr, nullptr);
     if (rc) break;
     stencil_grid g{};

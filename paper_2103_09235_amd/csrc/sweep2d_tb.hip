@@ -233,18 +233,8 @@ hipError_t launch_k<2, MASK_DIAMOND>(const SweepLaunch &L) {
   return hipErrorNotSupported;
 }
 template <>
-hipError_t launch_k<3, MASK_BOX>(const SweepLaunch &L) {
-  switch (L.steps) { TB_CASE(3, MASK_BOX, 2) }
-  return hipErrorNotSupported;
-}
-template <>
 hipError_t launch_k<3, MASK_DIAMOND>(const SweepLaunch &L) {
   switch (L.steps) { TB_CASE(3, MASK_DIAMOND, 2) }
-  return hipErrorNotSupported;
-}
-template <>
-hipError_t launch_k<4, MASK_BOX>(const SweepLaunch &L) {
-  switch (L.steps) { TB_CASE(4, MASK_BOX, 2) }
   return hipErrorNotSupported;
 }
 template <>
@@ -256,13 +246,18 @@ hipError_t launch_k<4, MASK_DIAMOND>(const SweepLaunch &L) {
 
 // Most steps per pass by radius: the queue (K*(2R+1)*4 registers) and two
 // groups of 2R+1 prefetched rows must leave room for two or more waves/SIMD.
-int tb_max(int R) { return R == 1 ? 8 : R == 2 ? 4 : R <= 4 ? 2 : 1; }
+// Boxes of radius 3 and more (49+ taps per point) are bound by FMA issue in
+// one step per pass already, and fusing only adds the redundant border work.
+int tb_max(int R, int mask) {
+  if (mask == MASK_BOX && R >= 3) return 1;
+  return R == 1 ? 8 : R == 2 ? 4 : R <= 4 ? 2 : 1;
+}
 
 }  // namespace
 
 int sweep2d_max_steps(const SweepLaunch &L) {
   const int R = L.op->R;
-  const int K = tb_max(R);
+  const int K = tb_max(R, L.op->mask);
   if (K < 2 || L.dtype != STENCIL_F32 || L.g.dim != 2) return 1;
   if (L.g.nx % kVX != 0 || L.g.nx < kSpan || L.g.ny < 2 * K * R + 1) return 1;
   if (L.g.nx > (1 << 30) || L.g.ny > (1 << 30)) return 1;
@@ -276,8 +271,8 @@ hipError_t launch_sweep2d_tb(const SweepLaunch &L) {
   switch (L.op->R) {
     case 1: return box ? launch_k<1, MASK_BOX>(L) : launch_k<1, MASK_DIAMOND>(L);
     case 2: return box ? launch_k<2, MASK_BOX>(L) : launch_k<2, MASK_DIAMOND>(L);
-    case 3: return box ? launch_k<3, MASK_BOX>(L) : launch_k<3, MASK_DIAMOND>(L);
-    case 4: return box ? launch_k<4, MASK_BOX>(L) : launch_k<4, MASK_DIAMOND>(L);
+    case 3: return box ? hipErrorNotSupported : launch_k<3, MASK_DIAMOND>(L);
+    case 4: return box ? hipErrorNotSupported : launch_k<4, MASK_DIAMOND>(L);
     default: return hipErrorNotSupported;
   }
 }

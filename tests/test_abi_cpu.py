@@ -192,6 +192,9 @@ def test_run_schedule_counts_launches():
     w4 = synth.random_positive_weights(2, 4, mask=synth.star_mask(2, 4))
     s = _sched(sf.Plan(w4, sf.STENCIL_STAR), (8192, 8192), 1001)
     assert (s["plain_launches"], s["final_copy"]) == (502, False)
+    # boxes of radius 3 and more are not fused (FMA-issue bound already)
+    b3 = synth.random_positive_weights(2, 3)
+    assert _sched(sf.Plan(b3, sf.STENCIL_BOX), (8192, 8192), 10)["plain_launches"] == 10
     # modes other than VECTOR run one application per launch in 2D
     star.set_mode(sf.STENCIL_MODE_SYMMETRIC)
     assert _sched(star, (8192, 8192), 1000)["plain_launches"] == 1000

@@ -378,9 +378,9 @@ TB_CASES = [
     ("star2d_m2_fused", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (150, 768), 16, 2, 0),
     ("box2d_m2_fused", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (64, 2048), 14, 2, 0),
     ("star_r3_plain", _star_weights(3, 300), sf.STENCIL_STAR, (90, 512), 6, 1, 0),
-    ("box2d_m3_fused", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (61, 764), 15, 3, 0),
+    ("box2d_m3_not_fused", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (61, 764), 15, 3, 0),
     ("star2d_m4_fused", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (300, 1024), 16, 4, 0),
-    ("box_r4_plain", _box_weights(4, 400), sf.STENCIL_BOX, (17, 256), 4, 1, 0),
+    ("box_r4_not_fused", _box_weights(4, 400), sf.STENCIL_BOX, (17, 256), 4, 1, 0),
 ]
 
 
