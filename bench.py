@@ -70,8 +70,8 @@ def parse():
     return ap.parse_args()
 
 
-# Source files each kernel family is built from (plus internal.h): a
-# committed PMC summary stays valid while these are unchanged.
+# Source files holding each kernel family's device code: a committed PMC
+# summary stays valid while these are unchanged.
 KERNEL_SOURCES = {
     "sweep1d": ("sweep1d.hip",),
     "sweep2d": ("sweep2d.hip", "sweep2d_impl.h", "sweep2d_launch.h", "sweep2d_r1.hip",
@@ -91,7 +91,7 @@ def kernel_family(kernel_key: str) -> str:
 def kernel_source_hash(family: str) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2103_09235_amd", "csrc")
-    for name in ("internal.h",) + KERNEL_SOURCES[family]:
+    for name in KERNEL_SOURCES[family]:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
