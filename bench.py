@@ -55,13 +55,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="star2d",
-                    choices=["star2d", "heat1d", "star3d", "box3d", "box2d", "batched"])
+                    choices=["star2d", "heat1d", "star3d", "box3d", "box2d", "unitbox2d",
+                             "batched"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only-m", type=int, default=0,
                     help="time only this fold depth (profiling runs)")
     ap.add_argument("--only-mode", default="",
-                    choices=["", "vector", "vector_unfused", "symmetric", "mfma_bf16x3"],
+                    choices=["", "vector", "vector_unfused", "symmetric", "separable",
+                             "mfma_bf16x3"],
                     help="time only this kernel family (profiling runs)")
     ap.add_argument("--no-per-grid", action="store_true",
                     help="batched: skip the per-grid-launch baseline (profiling runs)")
@@ -74,13 +76,13 @@ def parse():
 # summary stays valid while these are unchanged.
 KERNEL_SOURCES = {
     "sweep1d": ("sweep1d.hip",),
-    "sweep2d": ("sweep2d.hip", "sweep2d_impl.h", "sweep2d_launch.h", "sweep2d_r1.hip",
-                "sweep2d_r2.hip", "sweep2d_r3.hip", "sweep2d_r4.hip", "sweep2d_r5.hip",
-                "sweep2d_r6.hip", "sweep2d_r7.hip", "sweep2d_r8.hip"),
-    "sweep2dtb": ("sweep2d_tb.hip", "sweep2d_impl.h"),
+    "sweep2d": ("sweep2d.hip", "sweep2d_common.h", "sweep2d_impl.h", "sweep2d_launch.h",
+                "sweep2d_r1.hip", "sweep2d_r2.hip", "sweep2d_r3.hip", "sweep2d_r4.hip",
+                "sweep2d_r5.hip", "sweep2d_r6.hip", "sweep2d_r7.hip", "sweep2d_r8.hip"),
+    "sweep2dtb": ("sweep2d_tb.hip", "sweep2d_common.h"),
     "sweep3d": ("sweep3d.hip",),
     "mfma2d": ("mfma2d.hip",),
-    "batched": ("batched.hip", "sweep2d_impl.h"),
+    "batched": ("batched.hip", "sweep2d_common.h", "sweep2d_impl.h"),
 }
 
 
@@ -218,7 +220,13 @@ def bench_grid(args, wl_name):
                 form_modes.append(("vector_unfused", sf.STENCIL_MODE_VECTOR, 1))
         if symmetric:
             form_modes.append(("symmetric", sf.STENCIL_MODE_SYMMETRIC, 0))
-        if wl_name == "box2d" and m > 1:
+        if wl.dim == 2 and f32 and m > 1:
+            probe = sf.Plan(w, wl.shape_kind)
+            probe.fold(m)
+            if probe.separable()[1]:
+                form_modes.append(("separable", sf.STENCIL_MODE_SEPARABLE, 0))
+            probe.close()
+        if wl_name in ("box2d", "unitbox2d") and m > 1:
             form_modes.append(("mfma_bf16x3", sf.STENCIL_MODE_MFMA_BF16X3, 0))
         for mode_name, mode, fusion in form_modes:
             if args.only_mode and mode_name != args.only_mode:
@@ -264,7 +272,13 @@ def bench_grid(args, wl_name):
             launch_ms = el / args.steps / launches * 1e3
             algo_bytes = 2 * esz * n
             taps = int(np.count_nonzero(plan.fold(m) if m > 1 else w))
-            flops = 2 * taps * n * per_launch
+            # flops the form executes per point: one FMA per tap, or for the
+            # separable form 2 * rank * (2R+1) (a horizontal and a vertical
+            # pass per rank-one term)
+            fmas = taps
+            if mode_name == "separable":
+                fmas = 2 * plan.separable()[0] * (2 * m * ((w.shape[0] - 1) // 2) + 1)
+            flops = 2 * fmas * n * per_launch
             key = "%s_m%d_%s" % (wl_name, m, mode_name)
             forms[key] = {
                 "m": m, "mode": mode_name, "gstencil_s": round(gst, 2),
@@ -272,6 +286,7 @@ def bench_grid(args, wl_name):
                 "launches_per_run": launches,
                 "applications_per_launch": round(per_launch, 3),
                 "ms_per_launch": round(launch_ms, 5), "taps": taps,
+                "fmas_per_point": fmas,
                 "hbm_gbs_algorithmic": round(algo_bytes / (launch_ms / 1e3) / 1e9, 1),
                 "hbm_frac": round(algo_bytes / (launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                 "alu_tflops": round(flops / (launch_ms / 1e3) / 1e12, 2),
@@ -297,7 +312,9 @@ def bench_grid(args, wl_name):
         peak_t, basis = FP64_VECTOR_TFLOPS, "FP64 vector, published"
     ridge = peak_t * 1e12 / (HBM_PEAK_GBS * 1e9)
     dur = launch_ms / 1e3
-    if intensity < ridge or mode_name.startswith("mfma"):
+    # the matrix-core form is priced against HBM (its MFMA rate is far from
+    # bound); the symmetric form executes fewer operations than its taps
+    if intensity < ridge or mode_name in ("mfma_bf16x3", "symmetric"):
         roof = {"bound": "hbm", "achieved": round(algo_bytes / dur / 1e9, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     else:
@@ -310,6 +327,7 @@ def bench_grid(args, wl_name):
     tkey = {"vector": ("sweep%dd%s_m%d" % (wl.dim, "tb" if fused else "", m)),
             "vector_unfused": "sweep%dd_m%d" % (wl.dim, m),
             "symmetric": "sweep%dd_m%d_symmetric" % (wl.dim, m),
+            "separable": "sweep%dd_m%d_separable" % (wl.dim, m),
             "mfma_bf16x3": "mfma2d_m%d" % m}[mode_name]
     roof["traffic"] = traffic_from_profiles(tkey, wl_name)
     roof["kernel"] = "%s R=%d (%s, %d taps, %.2f applications per launch)" % (
@@ -319,6 +337,8 @@ def bench_grid(args, wl_name):
     roof["launch_ms"] = round(launch_ms, 5)
     roof["algorithmic_bytes_per_launch"] = algo_bytes
     roof["algorithmic_flops_per_launch"] = flops
+    roof["flops_basis"] = ("2 x FMAs per point (dense taps; 2 x rank x (2R+1) for the separable "
+                           "form) x points x applications per launch")
     roof["hbm_frac"] = round(algo_bytes / dur / 1e9 / HBM_PEAK_GBS, 4)
     res = {
         "metric": METRIC,

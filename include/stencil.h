@@ -46,10 +46,15 @@ enum {
   STENCIL_MODE_VECTOR = 0,      /* tiled vector kernels (default)            */
   STENCIL_MODE_EXACT_ORDER = 1, /* one thread per point, canonical order     */
   STENCIL_MODE_MFMA_BF16X3 = 2, /* 2D box folds as BF16 hi+lo MFMA products */
-  STENCIL_MODE_SYMMETRIC = 3    /* 2D operators symmetric in x and y: mirrored
+  STENCIL_MODE_SYMMETRIC = 3,   /* 2D operators symmetric in x and y: mirrored
                                    inputs summed once and each row's partial
                                    sum shared by two output rows (Section 3.3,
                                    Eq. 4-6); other operators run as VECTOR   */
+  STENCIL_MODE_SEPARABLE = 4    /* 2D operators of rank 1 or 2 as sums of
+                                   separable terms: a horizontal then a
+                                   vertical 1D pass per term (the vertical and
+                                   horizontal folding of Section 3.3, Eq. 4-6);
+                                   other operators run as VECTOR             */
 };
 enum {
   STENCIL_OK = 0,
@@ -125,9 +130,13 @@ int stencil_fold_weights_f32(stencil_plan p, float *out, int64_t *out_len);
  * MFMA_BF16X3 requires a 2D plan; runs with it accept FP32 grids only.
  * SYMMETRIC requires a 2D plan; it applies to operators with
  * w[dy][dx] == w[dy][-dx] == w[-dy][dx] on grids whose rows are whole
- * 16-byte vectors, and otherwise runs the VECTOR kernels.  VECTOR and
- * EXACT_ORDER keep the canonical summation order (acc = +0, one FMA per tap,
- * row-major offsets); MFMA_BF16X3 and SYMMETRIC do not.
+ * 16-byte vectors, and otherwise runs the VECTOR kernels.  SEPARABLE requires
+ * a 2D plan; it applies to FP32 grids whose rows are whole 16-byte vectors
+ * when stencil_plan_separable reports that it applies (radius m*r from 2 to
+ * 8), with factors rounded to FP32 keeping each factor's sum, and otherwise
+ * runs the VECTOR kernels.  VECTOR and EXACT_ORDER keep the canonical
+ * summation order (acc = +0, one FMA per tap, row-major offsets);
+ * MFMA_BF16X3, SYMMETRIC and SEPARABLE do not.
  * Errors: E_ARG, E_UNSUPPORTED.
  */
 int stencil_plan_set_mode(stencil_plan p, int mode);
@@ -143,6 +152,18 @@ int stencil_plan_set_mode(stencil_plan p, int mode);
  * Errors: E_ARG.  No device work.
  */
 int stencil_plan_set_fusion(stencil_plan p, int max_steps);
+
+/*
+ * stencil_plan_separable -- rank of the plan's current 2D operator (W_m, or
+ * w when unfolded) as a matrix W[dy][dx], by Gaussian elimination with
+ * complete pivoting in FP64 (pivots at most 1e-12 of the largest weight end
+ * it), and whether STENCIL_MODE_SEPARABLE applies it: rank 1 or 2 and
+ * 2 * rank * (2mr+1) FMAs per point fewer than its nonzero taps.  The
+ * paper's unit box folds to rank 1 for every m (Section 3.3, Eq. 4); the
+ * 5-point star folds to rank m+1.  rank and applies are nullable; a plan of
+ * another dimension reports 0 and 0.  Errors: E_ARG.  No device work.
+ */
+int stencil_plan_separable(stencil_plan p, int *rank, int *applies);
 
 /*
  * stencil_plan_info -- read back plan parameters (any pointer may be NULL):

@@ -20,6 +20,7 @@ STENCIL_PERIODIC, STENCIL_DIRICHLET = 0, 1
 STENCIL_F32, STENCIL_F64 = 0, 1
 STENCIL_MODE_VECTOR, STENCIL_MODE_EXACT_ORDER, STENCIL_MODE_MFMA_BF16X3 = 0, 1, 2
 STENCIL_MODE_SYMMETRIC = 3
+STENCIL_MODE_SEPARABLE = 4
 STENCIL_OK = 0
 STENCIL_E_ARG = -1
 STENCIL_E_UNSUPPORTED = -2
@@ -30,7 +31,8 @@ STENCIL_E_STATE = -5
 # Symbols include/stencil.h declares.
 EXPORTS = (
     "stencil_plan_create", "stencil_fold_weights", "stencil_fold_weights_f32",
-    "stencil_plan_set_mode", "stencil_plan_set_fusion", "stencil_plan_info",
+    "stencil_plan_set_mode", "stencil_plan_set_fusion", "stencil_plan_separable",
+    "stencil_plan_info",
     "stencil_profitability", "stencil_run", "stencil_run_schedule", "stencil_run_batched", "stencil_residual",
     "stencil_plan_destroy", "stencil_last_error", "stencil_version",
 )
@@ -85,6 +87,7 @@ def _load() -> ctypes.CDLL:
     lib.stencil_fold_weights_f32.argtypes = [P, fp, i64p]
     lib.stencil_plan_set_mode.argtypes = [P, ctypes.c_int]
     lib.stencil_plan_set_fusion.argtypes = [P, ctypes.c_int]
+    lib.stencil_plan_separable.argtypes = [P, ip, ip]
     lib.stencil_plan_info.argtypes = [P, ip, ip, ip, ip, ip]
     lib.stencil_profitability.argtypes = [P, ctypes.c_int, i64p, i64p]
     lib.stencil_run.argtypes = [P, ctypes.POINTER(stencil_grid), ctypes.c_int64]
@@ -154,6 +157,13 @@ def stencil_plan_set_mode(plan, mode: int) -> None:
 
 def stencil_plan_set_fusion(plan, max_steps: int) -> None:
     _check(lib.stencil_plan_set_fusion(plan, max_steps))
+
+
+def stencil_plan_separable(plan):
+    """(rank of the current 2D operator, whether SEPARABLE mode applies it)."""
+    rank, applies = ctypes.c_int(), ctypes.c_int()
+    _check(lib.stencil_plan_separable(plan, ctypes.byref(rank), ctypes.byref(applies)))
+    return rank.value, bool(applies.value)
 
 
 def stencil_plan_info(plan) -> dict:
@@ -286,6 +296,9 @@ class Plan:
 
     def set_fusion(self, max_steps: int) -> None:
         stencil_plan_set_fusion(self.handle, max_steps)
+
+    def separable(self):
+        return stencil_plan_separable(self.handle)
 
     def info(self) -> dict:
         return stencil_plan_info(self.handle)

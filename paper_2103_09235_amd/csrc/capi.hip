@@ -122,6 +122,34 @@ int build_operator(const std::vector<T> &w, int dim, int R, int mask,
 }
 
 // Operators for the current fold depth and dtype on the current device.
+// The separable form of a 2D operator W (FP64, side S): its rank (up to S)
+// and whether mode SEPARABLE applies it: rank 1 or 2 and 2 * rank * S FMAs
+// per point fewer than W's nonzero taps.
+bool separable_form(const std::vector<double> &W, int S, int *rank_out,
+                    std::vector<double> *a, std::vector<double> *b) {
+  std::vector<double> fa, fb;
+  const int rank = low_rank_2d(W, S, S, fa, fb);
+  int taps = 0;
+  for (double v : W) taps += v != 0.0;
+  if (rank_out) *rank_out = rank;
+  if (a) *a = fa;
+  if (b) *b = fb;
+  return rank >= 1 && rank <= 2 && 2 * rank * S < taps;
+}
+
+void attach_separable(const std::vector<double> &W, int R, OperatorDev &op) {
+  const int S = 2 * R + 1;
+  std::vector<double> a, b;
+  int rank = 0;
+  op.sep_rank = 0;
+  op.sep32.clear();
+  if (!separable_form(W, S, &rank, &a, &b)) return;
+  std::vector<double> f = a;
+  f.insert(f.end(), b.begin(), b.end());
+  round_factors_f32(f, S, op.sep32);
+  op.sep_rank = rank;
+}
+
 int ensure_operators(stencil_plan p, int device, int dtype) {
   DeviceState &d = p->dev[device];
   if (d.ready_m != p->m) {
@@ -136,6 +164,10 @@ int ensure_operators(stencil_plan p, int device, int dtype) {
     if (rc) return rc;
     rc = build_operator(p->Wm32, p->dim, R, mask_for(p->shape, p->m), d.fold32);
     if (rc) return rc;
+    if (p->dim == 2) {
+      attach_separable(p->w, p->r, d.plain32);
+      attach_separable(p->Wm, R, d.fold32);
+    }
     d.ready32 = true;
   }
   if (dtype == STENCIL_F64 && !d.ready64) {
@@ -156,6 +188,7 @@ hipError_t dispatch(stencil_plan p, const SweepLaunch &L) {
   else if (L.g.dim == 2) {
     SweepLaunch Ls = L;
     Ls.sym = p->mode == STENCIL_MODE_SYMMETRIC;
+    Ls.sep = p->mode == STENCIL_MODE_SEPARABLE;
     e = L.steps > 1 ? launch_sweep2d_tb(Ls) : launch_sweep2d(Ls);
   }
   else e = launch_sweep3d(L);
@@ -293,13 +326,30 @@ int stencil_plan_set_mode(stencil_plan p, int mode) {
   set_error("");
   if (int rc = check_plan(p)) return rc;
   if (mode != STENCIL_MODE_VECTOR && mode != STENCIL_MODE_EXACT_ORDER &&
-      mode != STENCIL_MODE_MFMA_BF16X3 && mode != STENCIL_MODE_SYMMETRIC)
+      mode != STENCIL_MODE_MFMA_BF16X3 && mode != STENCIL_MODE_SYMMETRIC &&
+      mode != STENCIL_MODE_SEPARABLE)
     return fail(STENCIL_E_ARG, "unknown mode");
   if (mode == STENCIL_MODE_SYMMETRIC && p->dim != 2)
     return fail(STENCIL_E_UNSUPPORTED, "SYMMETRIC mode needs a 2D plan");
+  if (mode == STENCIL_MODE_SEPARABLE && p->dim != 2)
+    return fail(STENCIL_E_UNSUPPORTED, "SEPARABLE mode needs a 2D plan");
   if (mode == STENCIL_MODE_MFMA_BF16X3 && p->dim != 2)
     return fail(STENCIL_E_UNSUPPORTED, "MFMA mode needs a 2D plan");
   p->mode = mode;
+  return STENCIL_OK;
+}
+
+int stencil_plan_separable(stencil_plan p, int *rank, int *applies) {
+  set_error("");
+  if (int rc = check_plan(p)) return rc;
+  if (p->dim != 2) {
+    if (rank) *rank = 0;
+    if (applies) *applies = 0;
+    return STENCIL_OK;
+  }
+  const int R = p->m * p->r;
+  const bool ok = separable_form(p->m > 1 ? p->Wm : p->w, 2 * R + 1, rank, nullptr, nullptr);
+  if (applies) *applies = ok ? 1 : 0;
   return STENCIL_OK;
 }
 

@@ -10,6 +10,7 @@
 // host from it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstring>
@@ -135,6 +136,70 @@ void round_fold_f32(const std::vector<double> &w, const std::vector<double> &Wm,
   for (int64_t i = 0; i < (int64_t)out.size(); ++i)
     if (i != c) rest += (double)out[i];
   out[c] = (float)(target - rest);
+}
+
+// Low-rank form of a 2D operator (the algebra behind the paper's vertical
+// then horizontal folding, Section 3.3 Eq. 4-6: the folded unit box is the
+// outer product of two 1D folded weight vectors): W = sum_{j<rank} a_j b_j^T
+// by Gaussian elimination with complete pivoting on the S x S matrix
+// W[dy][dx].  Each step takes the largest remaining entry p at (i, k) and
+// removes the rank-one term col_k(E) row_i(E) / p; it stops when the largest
+// remaining entry is at most 1e-12 of the largest weight (or after
+// max_rank + 1 terms, reported as rank max_rank + 1).  The factors are
+// balanced: a_j = col / sqrt|p|, b_j = row * sign(p) / sqrt|p|.
+int low_rank_2d(const std::vector<double> &W, int S, int max_rank, std::vector<double> &a,
+                std::vector<double> &b) {
+  std::vector<double> E = W;
+  double scale = 0.0;
+  for (double v : E) scale = std::max(scale, std::fabs(v));
+  a.clear();
+  b.clear();
+  if (scale == 0.0) return 0;
+  int rank = 0;
+  while (rank <= max_rank) {
+    int pi = 0, pk = 0;
+    double best = -1.0;
+    for (int i = 0; i < S; ++i)
+      for (int k = 0; k < S; ++k)
+        if (std::fabs(E[i * S + k]) > best) {
+          best = std::fabs(E[i * S + k]);
+          pi = i;
+          pk = k;
+        }
+    if (best <= 1e-12 * scale) break;
+    const double p = E[pi * S + pk];
+    const double sq = std::sqrt(std::fabs(p));
+    std::vector<double> col(S), row(S);
+    for (int i = 0; i < S; ++i) col[i] = E[i * S + pk];
+    for (int k = 0; k < S; ++k) row[k] = E[pi * S + k];
+    for (int i = 0; i < S; ++i)
+      for (int k = 0; k < S; ++k) E[i * S + k] -= col[i] * row[k] / p;
+    for (int i = 0; i < S; ++i) a.push_back(col[i] / sq);
+    for (int k = 0; k < S; ++k) b.push_back(row[k] / (p < 0 ? -sq : sq));
+    ++rank;
+  }
+  return rank;
+}
+
+// FP32 factors with each vector's total kept: entries rounded to nearest,
+// then the centre entry set to fl32(sum64 - sum of the other rounded
+// entries), so the FP32 operator's total weight sum_j (sum a_j)(sum b_j)
+// stays that of W (the mean of the field does not drift).
+void round_factors_f32(const std::vector<double> &f, int S, std::vector<float> &out) {
+  const int n = (int)f.size() / S;
+  out.resize(f.size());
+  for (int j = 0; j < n; ++j) {
+    double total = 0.0, rest = 0.0;
+    for (int i = 0; i < S; ++i) {
+      total += f[j * S + i];
+      out[j * S + i] = (float)f[j * S + i];
+    }
+    const int c = S / 2;
+    if (out[j * S + c] == 0.0f) continue;
+    for (int i = 0; i < S; ++i)
+      if (i != c) rest += (double)out[j * S + i];
+    out[j * S + c] = (float)(total - rest);
+  }
 }
 
 uint16_t bf16_rne(float x) {

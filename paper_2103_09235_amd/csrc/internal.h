@@ -52,6 +52,9 @@ struct OperatorDev {
   std::vector<double> w64;
   void *mfma_b = nullptr;    // BF16 hi/lo B-fragment table (2D FP32, R <= 8)
   bool symmetric = false;    // 2D: w[dy][dx] == w[dy][-dx] == w[-dy][dx]
+  int sep_rank = 0;          // 2D FP32: rank 1 or 2 of a separable form that is
+                             // cheaper than the dense taps, else 0
+  std::vector<float> sep32;  // its factors a_0.., then b_0.. (2R+1 each)
 };
 
 // Per-device state owned by a plan.
@@ -94,6 +97,12 @@ int fold_on_device(const std::vector<double> &w, int dim, int r, int m,
 void round_fold_f32(const std::vector<double> &w, const std::vector<double> &Wm,
                     int dim, int R, int m, std::vector<float> &out);
 uint16_t bf16_rne(float x);
+// W (S x S, row-major [dy][dx]) = sum_{j<rank} a_j b_j^T by complete-pivoting
+// elimination; returns the rank (max_rank + 1 if it is larger).
+int low_rank_2d(const std::vector<double> &W, int S, int max_rank, std::vector<double> &a,
+                std::vector<double> &b);
+// FP32 rounding of factor vectors (S each) keeping each vector's sum.
+void round_factors_f32(const std::vector<double> &f, int S, std::vector<float> &out);
 void profitability(const std::vector<double> &w, int dim, int r, int m,
                    int64_t *naive, int64_t *folded);
 
@@ -106,6 +115,7 @@ struct SweepLaunch {
   const OperatorDev *op = nullptr;
   int steps = 1;       // operator applications fused into this launch
   bool sym = false;    // mode SYMMETRIC: share mirrored partial sums if the operator allows
+  bool sep = false;    // mode SEPARABLE: low-rank form if the operator has one
   hipStream_t stream = nullptr;
 };
 

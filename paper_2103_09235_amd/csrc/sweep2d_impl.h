@@ -23,97 +23,10 @@
 
 #include <hip/hip_runtime.h>
 
-#include "internal.h"
+#include "sweep2d_common.h"
 
 namespace stencil {
 namespace k2d {
-
-// Weights passed by value in the kernel arguments (read through the
-// scalar cache), or from a uniform global pointer (batched tiles).
-template <typename T, int N>
-struct WArr {
-  T v[N];
-  __device__ __forceinline__ T operator[](int i) const { return v[i]; }
-};
-
-template <typename T>
-struct WPtr {
-  const T *__restrict__ p;
-  __device__ __forceinline__ T operator[](int i) const { return p[i]; }
-};
-
-__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-template <int MASK, int R>
-__host__ __device__ constexpr bool in_mask(int oy, int ox) {
-  return MASK == MASK_BOX ? true
-         : MASK == MASK_DIAMOND ? ((oy < 0 ? -oy : oy) + (ox < 0 ? -ox : ox) <= R)
-                                : (oy == 0 || ox == 0);
-}
-
-template <typename T, int VX>
-struct Vec {
-  T v[VX];
-};
-
-// Streaming accesses: every grid value is loaded once per sweep (halo rows
-// and columns aside) and every output stored once, so both use nontemporal
-// hints; on gfx950 this raises streaming bandwidth by about a tenth.
-template <typename T, int VX>
-__device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&d)[VX]) {
-  if constexpr (VX * sizeof(T) % 16 == 0) {
-    constexpr int E = 16 / sizeof(T);  // elements per 16-byte chunk
-    using V = __attribute__((ext_vector_type(E))) T;
-#pragma unroll
-    for (int c = 0; c < VX / E; ++c) {
-      V t = __builtin_nontemporal_load(reinterpret_cast<const V *>(p + c * E));
-#pragma unroll
-      for (int i = 0; i < E; ++i) d[c * E + i] = t[i];
-    }
-  } else if constexpr (VX * sizeof(T) == 8) {
-    using V = __attribute__((ext_vector_type(8 / sizeof(T)))) T;
-    V t = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
-#pragma unroll
-    for (int i = 0; i < VX; ++i) d[i] = t[i];
-  } else {
-#pragma unroll
-    for (int i = 0; i < VX; ++i) d[i] = __builtin_nontemporal_load(p + i);
-  }
-}
-
-template <typename T, int VX>
-__device__ __forceinline__ void store_vec(T *__restrict__ p, const T (&s)[VX]) {
-  if constexpr (VX * sizeof(T) % 16 == 0) {
-    constexpr int E = 16 / sizeof(T);
-    using V = __attribute__((ext_vector_type(E))) T;
-#pragma unroll
-    for (int c = 0; c < VX / E; ++c) {
-      V t;
-#pragma unroll
-      for (int i = 0; i < E; ++i) t[i] = s[c * E + i];
-      __builtin_nontemporal_store(t, reinterpret_cast<V *>(p + c * E));
-    }
-  } else if constexpr (VX * sizeof(T) == 8) {
-    using V = __attribute__((ext_vector_type(8 / sizeof(T)))) T;
-    V t;
-#pragma unroll
-    for (int i = 0; i < VX; ++i) t[i] = s[i];
-    __builtin_nontemporal_store(t, reinterpret_cast<V *>(p));
-  } else {
-#pragma unroll
-    for (int i = 0; i < VX; ++i) __builtin_nontemporal_store(s[i], p + i);
-  }
-}
-
-__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
-
-// Blocks are dealt round-robin to the 8 XCDs; renumber them so consecutive
-// tiles (which share halo rows and columns) run on the same XCD and L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-  if ((nb & 7) != 0) return b;
-  return (b & 7) * (nb >> 3) + (b >> 3);
-}
 
 template <int MASK, int R>
 __host__ __device__ constexpr int mask_taps() {
@@ -152,13 +65,21 @@ __host__ __device__ constexpr int lds_row(int) {
 // (Section 3.3, Eq. 4-6) instead of one FMA per tap.  Fewer operations
 // (28 instead of 41 per point for the folded 5-point star at m = 4), but not
 // the canonical order.
-template <typename T, int R, int MASK, int VX, int PD, bool STR, bool SYM, typename WA>
+//
+// SEPK > 0 (mode SEPARABLE): the operator is sum_{j<SEPK} a_j b_j^T (W holds
+// a_0..a_{SEPK-1}, then b_0..b_{SEPK-1}, S values each) and each input row
+// costs 2 * SEPK * S FMAs per point: the horizontal sum h_j = sum_dx
+// b_j[dx] u[x+dx], then a_j[oy] * h_j into each pending output row (the
+// paper's vertical and horizontal folding of a separable stencil, Eq. 4-6).
+template <typename T, int R, int MASK, int VX, int PD, bool STR, bool SYM, typename WA,
+          int SEPK = 0>
 __device__ __forceinline__ void sweep2d_tile(const T *__restrict__ in, T *__restrict__ out,
                                              int ny, int nx, int x0, int y0, int y1,
                                              const WA &W, T *lds) {
   constexpr int S = 2 * R + 1;
   constexpr int NU = S;
-  constexpr bool ROT = rotate_queue<MASK, R, VX>();
+  // the separable form's rows are short enough to unroll a whole queue turn
+  constexpr bool ROT = SEPK > 0 || rotate_queue<MASK, R, VX>();
   static_assert(ROT || PD == 1, "look-ahead needs the rotating queue");
   constexpr int UNR = ROT ? NU * PD : 1;
   constexpr int BX = 64 * VX;
@@ -264,7 +185,27 @@ __device__ __forceinline__ void sweep2d_tile(const T *__restrict__ in, T *__rest
           for (int i = RP + VX; i < VX + 2 * RP; ++i)
             win[0][i] = (i < RP + VX + R) ? L[lane * VX + i] : T(0);
         }
-        if constexpr (SYM) {
+        if constexpr (SEPK > 0) {
+          static_assert(!STR && !SYM, "separable rows use contiguous lanes");
+#pragma unroll
+          for (int jr = 0; jr < SEPK; ++jr) {
+            T h[VX];
+#pragma unroll
+            for (int ox = -R; ox <= R; ++ox) {
+              const T bt = W[(SEPK + jr) * S + ox + R];
+#pragma unroll
+              for (int v = 0; v < VX; ++v)
+                h[v] = fmat(bt, win[0][RP + v + ox], ox == -R ? T(0) : h[v]);
+            }
+#pragma unroll
+            for (int k = S - 1; k >= 0; --k) {
+              const int slot = (u + k) % NU;
+              const T at = W[jr * S + (R - k) + R];
+#pragma unroll
+              for (int v = 0; v < VX; ++v) acc[slot][v] = fmat(at, h[v], acc[slot][v]);
+            }
+          }
+        } else if constexpr (SYM) {
           static_assert(!STR, "shared partial sums use contiguous lanes");
           // sp[k][v] = u[x+k] + u[x-k] (sp[0] = u[x]) for the lane's columns
           T sp[R + 1][VX];
@@ -345,7 +286,7 @@ __device__ __forceinline__ void sweep2d_tile(const T *__restrict__ in, T *__rest
   }
 }
 
-template <typename T, int R, int MASK, int VX, int PD, bool STR, bool SYM>
+template <typename T, int R, int MASK, int VX, int PD, bool STR, bool SYM, int SEPK = 0>
 __global__ void __launch_bounds__(64)
 k_sweep2d(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
           int tiles_y, int tiles_x, int xfast, WArr<T, (2 * R + 1) * (2 * R + 1)> W) {
@@ -358,7 +299,8 @@ k_sweep2d(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
   const int x0 = tx * BX, y0 = ty * BY;
   const int y1 = min(y0 + BY, ny);
   __shared__ T lds[2 * lds_row<R, VX>(0)];
-  sweep2d_tile<T, R, MASK, VX, PD, STR, SYM>(in, out, ny, nx, x0, y0, y1, W, lds);
+  sweep2d_tile<T, R, MASK, VX, PD, STR, SYM, WArr<T, (2 * R + 1) * (2 * R + 1)>, SEPK>(
+      in, out, ny, nx, x0, y0, y1, W, lds);
 }
 
 }  // namespace k2d

@@ -10,12 +10,13 @@
 namespace stencil {
 namespace k2d {
 
-template <typename T, int R, int MASK, int VX, int PD, bool STR, bool SYM = false>
+template <typename T, int R, int MASK, int VX, int PD, bool STR, bool SYM = false, int SEPK = 0>
 hipError_t launch_one(const SweepLaunch &L, const std::vector<T> &w) {
   constexpr int S = 2 * R + 1;
   constexpr int BX = 64 * VX;
   WArr<T, S * S> W;
-  for (int i = 0; i < S * S; ++i) W.v[i] = w[i];
+  // dense weights, or SEPK pairs of separable factors (2 * SEPK * S < S * S)
+  for (int i = 0; i < S * S; ++i) W.v[i] = i < (int)w.size() ? w[i] : T(0);
   const int ny = (int)L.g.ny, nx = (int)L.g.nx;
   const int tiles_x = (nx + BX - 1) / BX;
   int by = 0;
@@ -37,7 +38,7 @@ hipError_t launch_one(const SweepLaunch &L, const std::vector<T> &w) {
     return e ? std::atoi(e) : -1;
   }();
   const int xfast = order_env >= 0 ? order_env : (R >= 3 ? 1 : 0);
-  hipLaunchKernelGGL((k_sweep2d<T, R, MASK, VX, PD, STR, SYM>), dim3((unsigned)blocks), dim3(64), 0,
+  hipLaunchKernelGGL((k_sweep2d<T, R, MASK, VX, PD, STR, SYM, SEPK>), dim3((unsigned)blocks), dim3(64), 0,
                      L.stream, (const T *)L.in, (T *)L.out, ny, nx, by, tiles_y, tiles_x,
                      xfast, W);
   return hipGetLastError();
@@ -50,6 +51,13 @@ hipError_t launch_vx(const SweepLaunch &L, const std::vector<T> &w) {
                        (L.g.nx % VXW == 0);
   // rows that are not whole vectors: strided lanes (coalesced scalars)
   if (!aligned) return launch_one<T, R, MASK, VXW, 1, true>(L, w);
+  // low-rank operators as sums of separable terms (mode SEPARABLE)
+  if constexpr (sizeof(T) == 4) {
+    if (L.sep && L.op->sep_rank == 1)
+      return launch_one<T, R, MASK_BOX, VXW, 1, false, false, 1>(L, L.op->sep32);
+    if (L.sep && L.op->sep_rank == 2 && 4 * (2 * R + 1) < (2 * R + 1) * (2 * R + 1))
+      return launch_one<T, R, MASK_BOX, VXW, 1, false, false, 2>(L, L.op->sep32);
+  }
   // mirror-symmetric operators may share partial sums (mode SYMMETRIC)
   if (L.sym && L.op->symmetric) {
     if constexpr (R <= 2) return launch_one<T, R, MASK, VXW, 2, false, true>(L, w);

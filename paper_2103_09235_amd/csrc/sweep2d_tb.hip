@@ -24,7 +24,7 @@
 #include <cstdlib>
 
 #include "internal.h"
-#include "sweep2d_impl.h"
+#include "sweep2d_common.h"
 
 namespace stencil {
 

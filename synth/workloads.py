@@ -139,6 +139,13 @@ def _make_workloads(seed: int = SEED) -> dict:
         to_f32_exact(random_positive_weights(2, 1, seed, STREAM_WEIGHTS)), (1, 4, 8),
         "2D 9-point random positive box, 16384^2 FP32, T=400; plain, fold m=4 "
         "(9x9) and m=8 (17x17), vector and BF16x3 MFMA")
+    # the paper's worked example (Section 3.3): the unit 9-point box, here
+    # normalised (each weight fl32(1/9)), whose folds are rank one
+    wl["unitbox2d"] = Workload(
+        "unitbox2d", 2, (16384, 16384), "f32", 400, BOX,
+        to_f32_exact(np.full((3, 3), 1.0 / 9.0)), (1, 4, 8),
+        "2D unit 9-point box (each weight 1/9), 16384^2 FP32, T=400; plain, fold m=4 "
+        "and m=8, dense, separable (rank one) and BF16x3 MFMA")
     return wl
 
 

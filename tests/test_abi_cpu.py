@@ -210,3 +210,31 @@ def test_run_schedule_counts_launches():
     with pytest.raises(sf.StencilError) as e:
         _sched(star, (2, 8192), 4)
     assert e.value.code == sf.STENCIL_E_UNSUPPORTED
+
+
+def test_separable_rank_and_mode():
+    """Rank of the operator by complete-pivoting elimination (host only) and
+    when the separable form applies (rank 1 or 2, fewer FMAs than taps)."""
+    unit = sf.Plan(np.ones((3, 3)) / 9.0, sf.STENCIL_BOX)
+    assert unit.separable() == (1, True)
+    assert sf.Plan(synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR).separable() == (2, False)
+    assert sf.Plan(synth.random_positive_weights(2, 1), sf.STENCIL_BOX).separable() == (3, False)
+    a = np.array([1.0, 2, 3, 2, 1])
+    b = np.array([1.0, 0, 2, 0, 1])
+    c = np.array([2.0, 1, 1, 1, 2])
+    assert sf.Plan(np.outer(a, b) / 81, sf.STENCIL_BOX).separable() == (1, True)
+    # rank 2 at radius 2: 2 * 2 * 5 = 20 FMAs < 25 taps
+    assert sf.Plan((np.outer(a, b) + np.outer(c, a)) / 200, sf.STENCIL_BOX).separable() == (2, True)
+    # rank 3 is never taken
+    d = np.array([0.0, 1, 0, 1, 0])
+    w3 = (np.outer(a, b) + np.outer(c, a) + np.outer(d, c)) / 300
+    assert sf.Plan(w3, sf.STENCIL_BOX).separable() == (3, False)
+    assert sf.Plan(np.ones((3, 3, 3)), sf.STENCIL_BOX).separable() == (0, False)
+    unit.set_mode(sf.STENCIL_MODE_SEPARABLE)
+    assert unit.info()["mode"] == sf.STENCIL_MODE_SEPARABLE
+    with pytest.raises(sf.StencilError) as e:
+        sf.Plan(np.ones((3, 3, 3)), sf.STENCIL_BOX).set_mode(sf.STENCIL_MODE_SEPARABLE)
+    assert e.value.code == sf.STENCIL_E_UNSUPPORTED
+    # SEPARABLE runs one application per launch
+    s = sf.stencil_run_schedule(unit.handle, (1024, 1024), sf.STENCIL_F32, 16, 1 << 20)
+    assert s["plain_launches"] == 16

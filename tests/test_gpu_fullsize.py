@@ -67,13 +67,14 @@ def run(w, kind, u0, T, m, mode=sf.STENCIL_MODE_VECTOR):
     ("star2d", 1, 6, "vector"), ("star2d", 2, 6, "vector"), ("star2d", 4, 8, "vector"),
     ("box2d", 4, 8, "vector"), ("box2d", 8, 8, "vector"), ("box2d", 4, 8, "mfma"),
     ("box2d", 8, 16, "mfma"), ("star3d", 2, 4, "vector"), ("box3d", 2, 4, "vector"),
-    ("box3d", 1, 3, "vector"),
+    ("box3d", 1, 3, "vector"), ("unitbox2d", 8, 16, "separable"), ("box2d", 1, 16, "vector"),
 ])
 def test_sampled_outputs_full_size(name, m, T, mode):
     wl = synth.WORKLOADS[name]
     print("full size", name, wl.shape, "m", m, "T", T, mode, flush=True)
     u0 = full_grid(name)
-    mcode = sf.STENCIL_MODE_MFMA_BF16X3 if mode == "mfma" else sf.STENCIL_MODE_VECTOR
+    mcode = {"mfma": sf.STENCIL_MODE_MFMA_BF16X3, "separable": sf.STENCIL_MODE_SEPARABLE,
+             "vector": sf.STENCIL_MODE_VECTOR}[mode]
     d = run(wl.weights, wl.shape_kind, u0, T, m, mcode)
     pts = sampled_points(wl.shape, 40, zlib.crc32(("%s-%d" % (name, m)).encode()))
     got = np.array([d[p].item() for p in pts], dtype=np.float32)
@@ -87,6 +88,11 @@ def test_sampled_outputs_full_size(name, m, T, mode):
                       for p in pts])
     err = np.max(np.abs(got - ref64)) / np.max(np.abs(ref64))
     assert err < (1e-3 if mode == "mfma" else 1e-5), err
+    if mode == "separable":
+        plan = sf.Plan(wl.weights, wl.shape_kind)
+        plan.fold(m)
+        assert plan.separable() == (1, True)
+        plan.close()
 
 
 @pytest.mark.parametrize("name,m", [("star2d", 4), ("star2d", 1), ("star3d", 2), ("box2d", 8)])

@@ -427,3 +427,54 @@ def test_run_schedule_folded_then_plain():
     torch.cuda.synchronize()
     assert np.array_equal(data.cpu().numpy(), oracle.folded_reference_f32(w, u0, 17, 4))
     plan.close()
+
+
+# ------------------------------------------------- separable (low-rank) form
+
+def _rank2_box():
+    a = np.array([1.0, 2, 3, 2, 1])
+    b = np.array([1.0, 0, 2, 0, 1])
+    c = np.array([2.0, 1, 1, 1, 2])
+    # a dyadic scale keeps the FP32 weights exactly rank two
+    return synth.to_f32_exact((np.outer(a, b) + np.outer(c, a)) / 256.0)
+
+
+SEP_CASES = [
+    # (name, weights, kind, shape, T, m, separable form used)
+    ("unitbox_m1", np.full((3, 3), 1.0 / 9.0), sf.STENCIL_BOX, (70, 512), 7, 1, True),
+    ("unitbox_m2", np.full((3, 3), 1.0 / 9.0), sf.STENCIL_BOX, (96, 768), 9, 2, True),
+    ("unitbox_m4", np.full((3, 3), 1.0 / 9.0), sf.STENCIL_BOX, (130, 1024), 18, 4, True),
+    ("unitbox_m8", np.full((3, 3), 1.0 / 9.0), sf.STENCIL_BOX, (120, 516), 19, 8, True),
+    ("unitbox_m8_min", np.full((3, 3), 1.0 / 9.0), sf.STENCIL_BOX, (17, 20), 16, 8, True),
+    ("rank2_r2", _rank2_box(), sf.STENCIL_BOX, (64, 260), 6, 1, True),
+    ("star2d_m2_dense", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (64, 512), 6, 2, False),
+    ("randbox_m4_dense", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (80, 512), 8, 4, False),
+    ("unitbox_m4_ragged", np.full((3, 3), 1.0 / 9.0), sf.STENCIL_BOX, (75, 301), 8, 4, False),
+]
+
+
+@pytest.mark.parametrize("case", SEP_CASES, ids=lambda c: c[0])
+def test_separable_mode(case):
+    """Rank-one/two operators as horizontal then vertical passes: within
+    1e-5 of the FP64 oracle (another summation order, factors rounded to
+    FP32); operators without a cheaper separable form, and rows that are not
+    whole vectors, run the canonical kernels and stay bit-exact."""
+    name, w, kind, shape, T, m, used = case
+    w = synth.to_f32_exact(w)
+    u0 = synth.grid_f32(shape)
+    plan = sf.Plan(w, kind)
+    if m > 1:
+        plan.fold(m)
+    plan.set_mode(sf.STENCIL_MODE_SEPARABLE)
+    print("separable", name, shape, "T", T, "m", m, plan.separable(), flush=True)
+    if name != "unitbox_m4_ragged":
+        assert plan.separable()[1] == used
+    data = torch.from_numpy(u0).to(DEV)
+    plan.run(data, T, torch.empty_like(data))
+    torch.cuda.synchronize()
+    got = data.cpu().numpy()
+    plan.close()
+    ref64 = oracle.sweep(w, u0.astype(np.float64), T)
+    assert oracle.errors(got, ref64)["e_rel"] < 1e-5
+    if not used:
+        assert np.array_equal(got, oracle.folded_reference_f32(w, u0, T, m))

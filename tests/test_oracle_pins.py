@@ -233,6 +233,27 @@ def test_paper_worked_fold_example():
     assert np.array_equal(c3, o3[0] * c2 + o3[1] * c1)
 
 
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 8])
+def test_folded_operator_ranks(m):
+    """The separable structure the separable mode relies on, checked on the
+    oracle's folds: the unit box folds to the outer product of the 1D folds
+    (rank one; its m = 2 instance is the paper's vertical then horizontal
+    folding, Eq. 4-6), a product stencil a b^T to (a^{*m})(b^{*m})^T, and the
+    5-point star, delta x h + v x delta with h, v 1D, to rank m + 1
+    (W_m = sum_k C(m,k) (v^{*k}) x (h^{*(m-k)}) with independent terms)."""
+    one = np.ones(3)
+    Wu = oracle.fold_weights(np.ones((3, 3)), m)
+    u1 = oracle.fold_weights(one, m)
+    assert np.array_equal(Wu, np.outer(u1, u1))
+    a, b = np.array([1.0, 2.0, 1.0]), np.array([3.0, 1.0, 2.0])
+    Wp = oracle.fold_weights(np.outer(a, b), m)
+    assert np.array_equal(Wp, np.outer(oracle.fold_weights(a, m), oracle.fold_weights(b, m)))
+    star = np.array([[0.0, 1, 0], [2, 3, 5], [0, 7, 0]])
+    Ws = oracle.fold_weights(star, m)
+    assert np.linalg.matrix_rank(Ws) == m + 1
+    assert np.linalg.matrix_rank(Wu) == 1
+
+
 def test_paper_profitability_counts():
     g = read_golden()
     naive, folded, ratio = oracle.collect_counts(np.ones((3, 3)), 2)
