@@ -19,6 +19,8 @@ from .core import (  # noqa: F401
     bf16_split,
     schedule,
     folded_reference_f32,
+    band_mask,
+    dirichlet_folded,
     errors,
     exact_sum,
     collect_counts,

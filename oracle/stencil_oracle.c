@@ -18,7 +18,10 @@
  *    w stored dense with shape (2r+1)^dim, indexed [r+oz][r+oy][r+ox];
  *  - periodic boundaries in every axis, wrap(i) = ((i mod n) + n) mod n,
  *    which is defined for any n >= 1 and any |o| (multiple wraps alias, as
- *    in the circulant operator);
+ *    in the circulant operator); or (the paper is silent on boundaries) zero
+ *    Dirichlet ghosts: every point outside the grid holds 0 at every step,
+ *    and a tap that reads one is skipped (fma(w, 0, acc) = acc for the
+ *    accumulators of this chain, which start at +0 and never become -0);
  *  - canonical operation order: acc = +0.0, then one fused multiply-add per
  *    nonzero tap in row-major offset order (oz, oy, ox ascending);
  *  - two arrays alternate between odd and even steps (Section 3.3, the
@@ -68,12 +71,14 @@ static int make_geom(int dim, const int64_t *shape, int r, geom_t *g) {
   return 0;
 }
 
-/* Per-axis table: tab[a][i + rad] = wrap(i) for i in [-rad, n + rad). */
-static int64_t *make_wrap_table(int64_t n, int rad) {
+/* Per-axis table: tab[a][i + rad] = wrap(i) for i in [-rad, n + rad), or
+ * with zero ghosts (boundary 1) i itself inside the grid and -1 outside. */
+static int64_t *make_wrap_table(int64_t n, int rad, int boundary) {
   int64_t len = n + 2 * (int64_t)rad;
   int64_t *t = (int64_t *)malloc(sizeof(int64_t) * (size_t)len);
   if (!t) return NULL;
-  for (int64_t i = -rad; i < n + rad; ++i) t[i + rad] = wrap_index(i, n);
+  for (int64_t i = -rad; i < n + rad; ++i)
+    t[i + rad] = boundary ? ((i >= 0 && i < n) ? i : -1) : wrap_index(i, n);
   return t;
 }
 
@@ -116,22 +121,23 @@ static void free_taps(taps_t *t) {
 }
 
 /*
- * oracle_sweep_f64: u_T = A^T u_0 with the canonical FMA chain, FP64.
+ * oracle_sweep_bc_f64: u_T = A^T u_0 with the canonical FMA chain, FP64.
  * dim in {1,2,3}; shape[dim] in numpy order (slowest first, x last);
- * w dense (2r+1)^dim; u0 and out hold prod(shape) values (they may alias).
+ * w dense (2r+1)^dim; u0 and out hold prod(shape) values (they may alias);
+ * boundary 0 = periodic, 1 = zero Dirichlet ghosts.
  * Returns 0, or -1 on bad arguments / allocation failure.
  */
-int oracle_sweep_f64(int dim, const int64_t *shape, int r, const double *w,
-                     const double *u0, int64_t T, double *out) {
+int oracle_sweep_bc_f64(int dim, const int64_t *shape, int r, const double *w,
+                        const double *u0, int64_t T, int boundary, double *out) {
   geom_t g;
-  if (make_geom(dim, shape, r, &g) || T < 0) return -1;
+  if (make_geom(dim, shape, r, &g) || T < 0 || boundary < 0 || boundary > 1) return -1;
   int64_t N = g.n[0] * g.n[1] * g.n[2];
   taps_t taps;
   double *a = (double *)malloc(sizeof(double) * (size_t)N);
   double *b = (double *)malloc(sizeof(double) * (size_t)N);
-  int64_t *tz = make_wrap_table(g.n[0], g.rad[0]);
-  int64_t *ty = make_wrap_table(g.n[1], g.rad[1]);
-  int64_t *tx = make_wrap_table(g.n[2], g.rad[2]);
+  int64_t *tz = make_wrap_table(g.n[0], g.rad[0], boundary);
+  int64_t *ty = make_wrap_table(g.n[1], g.rad[1], boundary);
+  int64_t *tx = make_wrap_table(g.n[2], g.rad[2], boundary);
   int rc = -1;
   if (!a || !b || !tz || !ty || !tx || make_taps_f64(&g, w, &taps)) goto done;
   memcpy(a, u0, sizeof(double) * (size_t)N);
@@ -146,6 +152,7 @@ int oracle_sweep_f64(int dim, const int64_t *shape, int r, const double *w,
             int64_t zz = tz[z + taps.oz[k] + g.rad[0]];
             int64_t yy = ty[y + taps.oy[k] + g.rad[1]];
             int64_t xx = tx[x + taps.ox[k] + g.rad[2]];
+            if (zz < 0 || yy < 0 || xx < 0) continue; /* zero ghost */
             acc = fma(w[taps.widx[k]], a[(zz * ny + yy) * nx + xx], acc);
           }
           b[(z * ny + y) * nx + x] = acc;
@@ -170,10 +177,10 @@ done:
  * oracle_sweep_f32: the same definition and operation order in FP32 (fmaf).
  * Weights are FP32 as the kernels hold them.
  */
-int oracle_sweep_f32(int dim, const int64_t *shape, int r, const float *w,
-                     const float *u0, int64_t T, float *out) {
+int oracle_sweep_bc_f32(int dim, const int64_t *shape, int r, const float *w,
+                        const float *u0, int64_t T, int boundary, float *out) {
   geom_t g;
-  if (make_geom(dim, shape, r, &g) || T < 0) return -1;
+  if (make_geom(dim, shape, r, &g) || T < 0 || boundary < 0 || boundary > 1) return -1;
   int64_t N = g.n[0] * g.n[1] * g.n[2];
   int sz = 2 * g.rad[0] + 1, sy = 2 * g.rad[1] + 1, sx = 2 * g.rad[2] + 1;
   int64_t W = (int64_t)sz * sy * sx;
@@ -181,9 +188,9 @@ int oracle_sweep_f32(int dim, const int64_t *shape, int r, const float *w,
   taps_t taps;
   float *a = (float *)malloc(sizeof(float) * (size_t)N);
   float *b = (float *)malloc(sizeof(float) * (size_t)N);
-  int64_t *tz = make_wrap_table(g.n[0], g.rad[0]);
-  int64_t *ty = make_wrap_table(g.n[1], g.rad[1]);
-  int64_t *tx = make_wrap_table(g.n[2], g.rad[2]);
+  int64_t *tz = make_wrap_table(g.n[0], g.rad[0], boundary);
+  int64_t *ty = make_wrap_table(g.n[1], g.rad[1], boundary);
+  int64_t *tx = make_wrap_table(g.n[2], g.rad[2], boundary);
   int rc = -1;
   if (!wd || !a || !b || !tz || !ty || !tx) goto done;
   for (int64_t k = 0; k < W; ++k) wd[k] = (double)w[k];
@@ -200,6 +207,7 @@ int oracle_sweep_f32(int dim, const int64_t *shape, int r, const float *w,
             int64_t zz = tz[z + taps.oz[k] + g.rad[0]];
             int64_t yy = ty[y + taps.oy[k] + g.rad[1]];
             int64_t xx = tx[x + taps.ox[k] + g.rad[2]];
+            if (zz < 0 || yy < 0 || xx < 0) continue; /* zero ghost */
             acc = fmaf(w[taps.widx[k]], a[(zz * ny + yy) * nx + xx], acc);
           }
           b[(z * ny + y) * nx + x] = acc;
@@ -219,4 +227,15 @@ done:
   free(ty);
   free(tx);
   return rc;
+}
+
+/* The periodic sweeps (boundary 0). */
+int oracle_sweep_f64(int dim, const int64_t *shape, int r, const double *w,
+                     const double *u0, int64_t T, double *out) {
+  return oracle_sweep_bc_f64(dim, shape, r, w, u0, T, 0, out);
+}
+
+int oracle_sweep_f32(int dim, const int64_t *shape, int r, const float *w,
+                     const float *u0, int64_t T, float *out) {
+  return oracle_sweep_bc_f32(dim, shape, r, w, u0, T, 0, out);
 }

@@ -9,6 +9,7 @@ worked example (tests/golden/paper_box9_m2.txt).
 """
 
 import itertools
+import zlib
 import math
 import os
 from fractions import Fraction
@@ -486,3 +487,103 @@ def test_pins_catch_dropped_fold_term():
     good = oracle.sweep(np.ones((3, 3)), u0, 2)
     assert np.array_equal(oracle.sweep(W, u0, 1), good)
     assert not np.array_equal(oracle.sweep(bad, u0, 1), good)
+
+
+# ------------------------------------------- zero Dirichlet ghosts (a reading)
+
+def brute_force_dirichlet(w, u0, T):
+    """A^T u0 with A the dense correlation operator whose taps that leave the
+    grid are dropped (points outside hold 0), exact arithmetic."""
+    shape = u0.shape
+    dim = len(shape)
+    r = (w.shape[0] - 1) // 2
+    rows = []
+    for x in itertools.product(*[range(n) for n in shape]):
+        row = {}
+        for o in itertools.product(range(-r, r + 1), repeat=dim):
+            wo = w[tuple(oi + r for oi in o)]
+            col = tuple(xi + oi for xi, oi in zip(x, o))
+            if wo == 0 or any(c < 0 or c >= n for c, n in zip(col, shape)):
+                continue
+            row[int(np.ravel_multi_index(col, shape))] = wo
+        rows.append(row)
+    vec = list(u0.ravel())
+    for _ in range(T):
+        vec = [sum(wv * vec[c] for c, wv in row.items()) for row in rows]
+    return np.array(vec, dtype=object).reshape(shape)
+
+
+@pytest.mark.parametrize("shape", [(1,), (2,), (5,), (9,), (1, 1), (3, 4), (6, 5), (2, 3, 4)])
+@pytest.mark.parametrize("r", [1, 2])
+def test_dirichlet_brute_force_integer_bit_exact(shape, r):
+    g = rng(zlib.crc32(repr((shape, r, "dirichlet")).encode()))
+    w = g.integers(-3, 4, size=(2 * r + 1,) * len(shape)).astype(np.float64)
+    u0 = g.integers(-5, 6, size=shape).astype(np.float64)
+    T = 3
+    ref = brute_force_dirichlet(w.astype(int).astype(object), u0.astype(int).astype(object), T)
+    got = oracle.sweep(w, u0, T, "zero")
+    assert np.array_equal(got, ref.astype(np.float64))
+
+
+@pytest.mark.parametrize("n,k", [(31, 1), (31, 5), (64, 17)])
+def test_dirichlet_sine_modes_heat1d(n, k):
+    """With zero ghosts, sin(pi k (i+1)/(n+1)) is an eigenvector of the 1D
+    heat operator (1/4, 1/2, 1/4) with eigenvalue cos^2(pi k / (2(n+1)))."""
+    i = np.arange(n)
+    v = np.sin(np.pi * k * (i + 1) / (n + 1))
+    lam = np.cos(np.pi * k / (2 * (n + 1))) ** 2
+    T = 40
+    got = oracle.sweep(synth.heat1d_weights(), v, T, "zero")
+    assert np.max(np.abs(got - lam ** T * v)) < 4 * T * 3 * EPS64
+
+
+def test_dirichlet_sine_modes_star2d():
+    """2D 5-point star (centre c, neighbours n): the product of sine modes is
+    an eigenvector with eigenvalue c + 2n (cos(theta_y) + cos(theta_x))."""
+    ny, nx, ky, kx = 21, 34, 3, 7
+    ty, tx = np.pi * ky / (ny + 1), np.pi * kx / (nx + 1)
+    v = np.outer(np.sin(ty * (np.arange(ny) + 1)), np.sin(tx * (np.arange(nx) + 1)))
+    c, nb = 0.6, 0.1
+    lam = c + 2 * nb * (np.cos(ty) + np.cos(tx))
+    T = 30
+    got = oracle.sweep(synth.star2d_weights(c, nb), v, T, "zero")
+    assert np.max(np.abs(got - lam ** T * v)) < 4 * T * 5 * EPS64
+
+
+@pytest.mark.parametrize("dim,r,m,shape", [
+    (1, 1, 2, (13,)), (1, 1, 4, (5,)), (1, 2, 3, (40,)),
+    (2, 1, 2, (9, 14)), (2, 1, 4, (17, 30)), (2, 2, 3, (23, 11)), (2, 1, 8, (12, 40)),
+    (3, 1, 2, (6, 7, 9)), (3, 1, 3, (11, 8, 10)),
+])
+def test_dirichlet_folding_reading_exact(dim, r, m, shape):
+    """The folded Dirichlet reading (W_m at least (m-1)r from every face, m
+    plain steps in the band) equals the plain zero-ghost sweep exactly on
+    integer data, for any T (folded applications then the remainder),
+    including grids narrower than twice the band."""
+    g = rng(dim * 100 + r * 10 + m)
+    w = g.integers(-2, 3, size=(2 * r + 1,) * dim).astype(np.float64)
+    u0 = g.integers(-4, 5, size=shape).astype(np.float64)
+    for T in (m, 2 * m + 1, 3 * m - 1):
+        assert np.array_equal(oracle.dirichlet_folded(w, u0, T, m), oracle.sweep(w, u0, T, "zero"))
+
+
+def test_dirichlet_pins_catch_a_narrow_band():
+    """A band one r narrower than (m-1)r (planted here, on the CPU) breaks
+    the exact equality the previous pin checks."""
+    w = np.array([[0.0, 1, 0], [2, 3, 1], [0, 2, 0]])
+    u0 = (np.arange(20 * 25).reshape(20, 25) % 7).astype(np.float64)
+    m, T = 4, 8
+    band = oracle.band_mask(u0.shape, (m - 2) * 1)
+    u = u0
+    for _ in range(T // m):
+        u = np.where(band, oracle.sweep(w, u, m, "zero"),
+                     oracle.sweep(oracle.fold_weights(w, m), u, 1, "zero"))
+    assert not np.array_equal(u, oracle.sweep(w, u0, T, "zero"))
+
+
+def test_dirichlet_mirror_f32_close_to_fp64():
+    w = synth.WORKLOADS["star2d"].weights
+    u0 = synth.grid_f32((40, 52))
+    got = oracle.dirichlet_folded(w, u0, 9, 4, f32=True)
+    ref = oracle.sweep(w, u0.astype(np.float64), 9, "zero")
+    assert oracle.errors(got, ref)["e_rel"] < 1e-6
