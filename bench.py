@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="star2d",
                     choices=["star2d", "heat1d", "star3d", "box3d", "box2d", "unitbox2d",
-                             "batched"])
+                             "star2d_dirichlet", "batched"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only-m", type=int, default=0,
@@ -132,7 +132,7 @@ def time_runs(fn, steps, warmup):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
-def cpu_baseline(w, shape_full, dtype, T_full, budget_s):
+def cpu_baseline(w, shape_full, dtype, T_full, budget_s, boundary="periodic"):
     """The oracle as it stands, timed on a bounded sample of the workload: a
     smaller grid of the same dimension and distribution, for a number of
     original steps chosen to fill about budget_s seconds."""
@@ -141,13 +141,13 @@ def cpu_baseline(w, shape_full, dtype, T_full, budget_s):
     import synth
     shape = tuple(shape_full)
     u0 = synth.grid_f64(shape)
-    oracle.sweep(w, u0, 1)  # warm: threads, page faults
+    oracle.sweep(w, u0, 1, boundary)  # warm: threads, page faults
     t0 = time.perf_counter()
-    oracle.sweep(w, u0, 2)
+    oracle.sweep(w, u0, 2, boundary)
     per_step = max((time.perf_counter() - t0) / 2, 1e-6)
     T = int(max(1, min(T_full, budget_s / per_step)))
     t0 = time.perf_counter()
-    oracle.sweep(w, u0, T)
+    oracle.sweep(w, u0, T, boundary)
     dt = time.perf_counter() - t0
     n = int(np.prod(shape))
     return {
@@ -160,12 +160,12 @@ def cpu_baseline(w, shape_full, dtype, T_full, budget_s):
     }
 
 
-def fp64_reference(sf, w, kind, u0, T):
+def fp64_reference(sf, w, kind, u0, T, boundary=0):
     """The same T steps in FP64 by the library's plain FP64 sweep, which the
     parity tests pin bit-for-bit to the FP64 oracle."""
     import numpy as np
     import torch
-    plan = sf.Plan(w, kind)
+    plan = sf.Plan(w, kind, boundary)
     d = torch.from_numpy(np.asarray(u0, dtype=np.float64)).cuda()
     plan.run(d, T)
     torch.cuda.synchronize()
@@ -190,6 +190,8 @@ def bench_grid(args, wl_name):
 
     wl = synth.WORKLOADS[wl_name]
     shape, T, w = wl.shape, wl.T, wl.weights
+    zero_bc = wl.extra.get("boundary") == "zero"
+    bc = sf.STENCIL_DIRICHLET if zero_bc else sf.STENCIL_PERIODIC
     f32 = wl.dtype == "f32"
     esz = 4 if f32 else 8
     n = int(np.prod(shape))
@@ -216,7 +218,7 @@ def bench_grid(args, wl_name):
         form_modes = []
         if m not in extra:
             form_modes.append(("vector", sf.STENCIL_MODE_VECTOR, 0))
-            if wl.dim == 2 and f32:
+            if wl.dim == 2 and f32 and not zero_bc:
                 form_modes.append(("vector_unfused", sf.STENCIL_MODE_VECTOR, 1))
         if symmetric:
             form_modes.append(("symmetric", sf.STENCIL_MODE_SYMMETRIC, 0))
@@ -231,7 +233,7 @@ def bench_grid(args, wl_name):
         for mode_name, mode, fusion in form_modes:
             if args.only_mode and mode_name != args.only_mode:
                 continue
-            plan = sf.Plan(w, wl.shape_kind)
+            plan = sf.Plan(w, wl.shape_kind, bc)
             if m > 1:
                 plan.fold(m)
             try:
@@ -257,12 +259,13 @@ def bench_grid(args, wl_name):
             s1, _, _ = sf.stencil_residual(data)
             w_eff = w.astype(np.float32).astype(np.float64) if f32 else w
             expect = math.fsum(float(v) for v in w_eff.ravel()) ** total_T * s0
-            mass_rel = abs(s1 - expect) / abs(expect)
+            # (zero boundaries lose mass through the faces: not an invariant)
+            mass_rel = None if zero_bc else abs(s1 - expect) / abs(expect)
             # error of one T-step run against the FP64 sweep
             data.copy_(torch.from_numpy(u0).to(dev))
             plan.run(data, T, scratch)
             if ref64 is None:
-                ref64 = fp64_reference(sf, w, wl.shape_kind, u0, T)
+                ref64 = fp64_reference(sf, w, wl.shape_kind, u0, T, bc)
             err, err_detr = error_vs(ref64, data)
             gst = n * T * args.steps / el / 1e9
             launches = sched["folded_launches"] + sched["plain_launches"]
@@ -295,8 +298,9 @@ def bench_grid(args, wl_name):
                 "wall_s": round(wall, 3),
             }
             log("[bench]   %.1f GStencil/s, %d launches of %.2f applications, %.4f ms/launch, "
-                "e_rel %.2e (detrended %.2e), mass drift %.2e" % (
-                    gst, launches, per_launch, launch_ms, err, err_detr, mass_rel))
+                "e_rel %.2e (detrended %.2e), mass drift %s" % (
+                    gst, launches, per_launch, launch_ms, err, err_detr,
+                    "n/a" if mass_rel is None else "%.2e" % mass_rel))
             forms[key]["stated_fold"] = m not in extra
             if m not in extra and (headline is None or gst > headline[1]):
                 headline = (key, gst, el, launch_ms, algo_bytes, flops, m, mode_name, taps,
@@ -360,7 +364,8 @@ def bench_grid(args, wl_name):
     }
     if not args.no_cpu:
         log("[bench] timing the CPU oracle baseline")
-        res["cpu_baseline"] = cpu_baseline(w, shape, wl.dtype, T, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(w, shape, wl.dtype, T, args.cpu_seconds,
+                                           "zero" if zero_bc else "periodic")
     return res
 
 

@@ -94,7 +94,12 @@ typedef struct {
  *   shape    STENCIL_STAR (weights off the axes must be zero) or STENCIL_BOX.
  *   weights  host, (2r+1)^dim finite FP64 values, copied (the caller may free
  *            them on return).
- *   boundary STENCIL_PERIODIC; STENCIL_DIRICHLET returns E_UNSUPPORTED.
+ *   boundary STENCIL_PERIODIC (every axis wraps) or STENCIL_DIRICHLET (every
+ *            point outside the grid holds 0 at every step; the paper states
+ *            no boundary, both are readings).  Folded zero-boundary runs
+ *            apply W_m at points at least (m-1)r from every face, where it
+ *            equals m plain zero-boundary steps exactly, and m plain steps in
+ *            the band nearer a face; see stencil_run.
  *   out      receives the plan; the plan starts unfolded (m = 1) in
  *            STENCIL_MODE_VECTOR.
  * Errors: E_ARG for a bad argument, E_UNSUPPORTED, E_NOMEM.  No device work.
@@ -193,8 +198,13 @@ int stencil_profitability(stencil_plan p, int m, int64_t *naive,
  * sweeps; if the number of sweeps is odd a final device copy puts the result
  * back into g->data.
  *   g->dtype F32 or F64 (MFMA mode: F32 only); g->dim must equal the plan's;
- *   every axis >= 2*m*r + 1 (else E_UNSUPPORTED).  T = 0 is a no-op; T < 0
- *   is E_ARG.  g->scratch, when given, must not overlap g->data.
+ *   periodic plans need every axis >= 2*m*r + 1 (else E_UNSUPPORTED),
+ *   zero-boundary plans any axis >= 1.  T = 0 is a no-op; T < 0 is E_ARG.
+ *   g->scratch, when given, must not overlap g->data.
+ * Zero-boundary (STENCIL_DIRICHLET) runs copy the grid into plan-owned
+ * buffers zero-padded by m*r on each face (four padded grids, kept for later
+ * runs), run each application there and copy the result back; g->scratch is
+ * not used and no application is fused.
  * Enqueued asynchronously on g->stream; the caller keeps data and scratch
  * alive until that work has completed.
  * Errors: E_ARG, E_UNSUPPORTED, E_STATE, E_NOMEM, E_DEVICE.

@@ -291,6 +291,8 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
     const stencil_grid &g = grids[i];
     if (!p || !g.data || !g.scratch) return fail(STENCIL_E_ARG, "NULL plan, data or scratch");
     if (p->dim != 2 || g.dim != 2) return fail(STENCIL_E_UNSUPPORTED, "batched runs are 2D");
+    if (p->boundary != STENCIL_PERIODIC)
+      return fail(STENCIL_E_UNSUPPORTED, "batched runs are periodic");
     if (g.dtype != STENCIL_F32) return fail(STENCIL_E_UNSUPPORTED, "batched runs are FP32");
     if (p->r > kMaxBatchRadius) return fail(STENCIL_E_UNSUPPORTED, "batched stencils need r <= 2");
     if (g.stream != grids[0].stream) return fail(STENCIL_E_ARG, "all grids must name one stream");

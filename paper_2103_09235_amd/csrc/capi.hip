@@ -65,6 +65,11 @@ void free_device_state(DeviceState &d) {
   if (d.scratch) (void)hipFree(d.scratch);
   d.scratch = nullptr;
   d.scratch_bytes = 0;
+  for (void *&b : d.dir_buf) {
+    if (b) (void)hipFree(b);
+    b = nullptr;
+  }
+  d.dir_bytes = 0;
   d.ready32 = d.ready64 = false;
   d.ready_m = 0;
 }
@@ -247,8 +252,6 @@ int stencil_plan_create(int dim, int radius, int shape, const double *weights,
     if (shape == STENCIL_STAR && weights[i] != 0.0 && !on_axes(i, dim, radius))
       return fail(STENCIL_E_ARG, "STAR stencil has a nonzero weight off the axes");
   }
-  if (boundary == STENCIL_DIRICHLET)
-    return fail(STENCIL_E_UNSUPPORTED, "only periodic boundaries are implemented");
   stencil_plan p = new (std::nothrow) stencil_plan_s();
   if (!p) return fail(STENCIL_E_NOMEM, "plan allocation failed");
   try {
@@ -413,7 +416,8 @@ int check_run(stencil_plan p, const stencil_grid *g, int64_t T, Geom &geo) {
   geo.nz = n[0];
   geo.ny = n[1];
   geo.nx = n[2];
-  const int64_t need = 2 * (int64_t)p->m * p->r + 1;
+  // periodic runs wrap once at most; zero-boundary runs pad the grid
+  const int64_t need = p->boundary == STENCIL_PERIODIC ? 2 * (int64_t)p->m * p->r + 1 : 1;
   for (int a = 0; a < p->dim; ++a)
     if (g->shape[a] < need)
       return fail(STENCIL_E_UNSUPPORTED,
@@ -445,7 +449,8 @@ Schedule make_schedule(stencil_plan p, const Geom &geo, int dtype, const void *d
   Schedule sc;
   sc.apps[0] = p->m > 1 ? T / p->m : 0;
   sc.apps[1] = p->m > 1 ? T % p->m : T;
-  const bool aligned = (uintptr_t)data % 16 == 0 && (uintptr_t)scratch % 16 == 0;
+  const bool aligned = (uintptr_t)data % 16 == 0 && (uintptr_t)scratch % 16 == 0 &&
+                       p->boundary == STENCIL_PERIODIC;
   int64_t kmax[2] = {1, 1};
   for (int i = 0; i < 2; ++i) {
     if (sc.apps[i] == 0) continue;
@@ -456,7 +461,9 @@ Schedule make_schedule(stencil_plan p, const Geom &geo, int dtype, const void *d
     L.g = geo;
     L.dtype = dtype;
     L.op = &op;
-    if (p->dim == 1 && p->mode != STENCIL_MODE_EXACT_ORDER)
+    if (p->boundary != STENCIL_PERIODIC)
+      kmax[i] = 1;  // the zero pad is restored after every application
+    else if (p->dim == 1 && p->mode != STENCIL_MODE_EXACT_ORDER)
       kmax[i] = std::max(1, sweep1d_max_steps(L));
     else if (p->dim == 2 && p->mode == STENCIL_MODE_VECTOR && aligned)
       kmax[i] = std::max(1, sweep2d_max_steps(L));
@@ -467,8 +474,92 @@ Schedule make_schedule(stencil_plan p, const Geom &geo, int dtype, const void *d
     if ((sc.launches[0] + sc.launches[1]) % 2 == 0) break;
     if (kmax[i] > 1 && sc.launches[i] < sc.apps[i]) sc.launches[i] += 1;
   }
-  sc.final_copy = (sc.launches[0] + sc.launches[1]) % 2 == 1;
+  sc.final_copy = (sc.launches[0] + sc.launches[1]) % 2 == 1 ||
+                  (p->boundary != STENCIL_PERIODIC && T > 0);
   return sc;
+}
+
+// A zero-boundary run (reading in dirichlet.hip): the grid is copied into a
+// zero-padded buffer (pad P = m*r on the grid's axes, rows rounded up to
+// whole 256-byte lines), each application runs the periodic kernels on the
+// padded grid, then restores the zero pad; a folded application also
+// recomputes the band closer than (m-1)r to a face from m plain steps on a
+// frame of width 2(m-1)r.  The result is copied back into g->data; g->scratch
+// is not used.
+int run_dirichlet(stencil_plan p, stencil_grid *g, int64_t T, const Geom &geo, DeviceState &d) {
+  const int dim = p->dim, m = p->m, r = p->r;
+  const int dtype = g->dtype;
+  const size_t es = esize(dtype);
+  const int64_t P = (int64_t)m * r;
+  const int64_t n[3] = {geo.nz, geo.ny, geo.nx};
+  int64_t np[3], off[3];
+  for (int a = 0; a < 3; ++a) {
+    const bool axis = a >= 3 - dim;
+    off[a] = axis ? P : 0;
+    np[a] = axis ? n[a] + 2 * P : 1;
+  }
+  // padded rows in whole 256-byte lines (aligned row segments for the tiles)
+  const int64_t line = 256 / (int64_t)es;
+  np[2] = (np[2] + line - 1) / line * line;
+  const size_t bytes = (size_t)(np[0] * np[1] * np[2]) * es;
+  if (d.dir_bytes < bytes) {
+    if (d.dir_bytes) STENCIL_HIP_TRY(hipDeviceSynchronize());
+    for (void *&b : d.dir_buf) {
+      if (b) (void)hipFree(b);
+      b = nullptr;
+    }
+    d.dir_bytes = 0;
+    for (void *&b : d.dir_buf) STENCIL_HIP_TRY(hipMalloc(&b, bytes));
+    d.dir_bytes = bytes;
+  }
+  hipStream_t s = (hipStream_t)g->stream;
+  const OperatorDev &plain = dtype == STENCIL_F32 ? d.plain32 : d.plain64;
+  const OperatorDev &folded = dtype == STENCIL_F32 ? d.fold32 : d.fold64;
+  void *A = d.dir_buf[0], *B = d.dir_buf[1];
+  void *F[2] = {d.dir_buf[2], d.dir_buf[3]};
+  const int64_t ibase = (off[0] * np[1] + off[1]) * np[2] + off[2];
+  hipError_t e = dirichlet_box_copy(g->data, 0, n[1] * n[2], n[2], A, ibase, np[1] * np[2],
+                                    np[2], n, dtype, s);
+  // pads cleared on every run: the buffers may hold another geometry's data
+  for (void *b : {A, F[0], F[1]})
+    if (e == hipSuccess) e = dirichlet_clear_pad(b, np, off, n, dtype, s);
+  if (e != hipSuccess) return hip_fail(e, "zero-boundary set-up");
+  Geom pg;
+  pg.dim = dim;
+  pg.nz = np[0];
+  pg.ny = np[1];
+  pg.nx = np[2];
+  SweepLaunch L;
+  L.g = pg;
+  L.dtype = dtype;
+  L.stream = s;
+  L.steps = 1;
+  const int64_t q = m > 1 ? T / m : 0;
+  const int64_t rem = m > 1 ? T % m : T;
+  const int64_t Wb = (int64_t)(m - 1) * r, Wf = 2 * Wb;
+  for (int64_t k = 0; k < q + rem; ++k) {
+    const bool fold = k < q;
+    L.op = fold ? &folded : &plain;
+    L.in = A;
+    L.out = B;
+    e = dispatch(p, L);
+    if (e == hipSuccess && fold && m > 1) {
+      // levels 1 .. m-1 on the frame, level m into the band of B
+      const void *src = A;
+      for (int j = 1; j < m && e == hipSuccess; ++j) {
+        e = dirichlet_frame_step(src, F[(j - 1) & 1], np, off, n, Wf, plain, dtype, s);
+        src = F[(j - 1) & 1];
+      }
+      if (e == hipSuccess) e = dirichlet_frame_step(src, B, np, off, n, Wb, plain, dtype, s);
+    }
+    if (e == hipSuccess) e = dirichlet_clear_pad(B, np, off, n, dtype, s);
+    if (e != hipSuccess) return hip_fail(e, "zero-boundary sweep");
+    std::swap(A, B);
+  }
+  e = dirichlet_box_copy(A, ibase, np[1] * np[2], np[2], g->data, 0, n[1] * n[2], n[2], n, dtype,
+                         s);
+  if (e != hipSuccess) return hip_fail(e, "zero-boundary copy-back");
+  return STENCIL_OK;
 }
 
 }  // namespace
@@ -507,6 +598,7 @@ int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
   }
   if (int rc = ensure_operators(p, device, g->dtype)) return rc;
   DeviceState &d = p->dev[device];
+  if (p->boundary == STENCIL_DIRICHLET) return run_dirichlet(p, g, T, geo, d);
   void *scratch = g->scratch;
   if (!scratch) {
     if (d.scratch_bytes < bytes) {

@@ -64,6 +64,8 @@ struct DeviceState {
   int ready_m = 0;
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
+  void *dir_buf[4] = {nullptr, nullptr, nullptr, nullptr};  // zero-boundary runs:
+  size_t dir_bytes = 0;      // two padded grids and two padded frame buffers
   std::map<std::string, hipGraphExec_t> graphs;
   std::map<std::string, hipGraph_t> graph_src;
 };
@@ -137,6 +139,18 @@ int sweep1d_max_steps(const SweepLaunch &L);
 // the launch of 2 <= L.steps <= that many steps.
 int sweep2d_max_steps(const SweepLaunch &L);
 hipError_t launch_sweep2d_tb(const SweepLaunch &L);
+
+// Zero-boundary runs (dirichlet.hip).  Padded arrays have extents np, the
+// interior starting at off with extents n (z, y, x).
+hipError_t dirichlet_box_copy(const void *src, int64_t sbase, int64_t ssz, int64_t ssy, void *dst,
+                              int64_t dbase, int64_t dsz, int64_t dsy, const int64_t e[3],
+                              int dtype, hipStream_t s);
+// One plain step at the interior points closer than W to a face.
+hipError_t dirichlet_frame_step(const void *src, void *dst, const int64_t np[3],
+                                const int64_t off[3], const int64_t n[3], int64_t W,
+                                const OperatorDev &op, int dtype, hipStream_t s);
+hipError_t dirichlet_clear_pad(void *dst, const int64_t np[3], const int64_t off[3],
+                               const int64_t n[3], int dtype, hipStream_t s);
 
 // FP64 fold convolution: out = a (radius Ra) * w (radius r), dim d.
 hipError_t launch_fold_conv(const double *a, int Ra, const double *w, int r,

@@ -139,6 +139,13 @@ def _make_workloads(seed: int = SEED) -> dict:
         to_f32_exact(random_positive_weights(2, 1, seed, STREAM_WEIGHTS)), (1, 4, 8),
         "2D 9-point random positive box, 16384^2 FP32, T=400; plain, fold m=4 "
         "(9x9) and m=8 (17x17), vector and BF16x3 MFMA")
+    # the star2d workload with zero Dirichlet boundaries (the paper states no
+    # boundary; zero ghosts are the reading measured beside the periodic one)
+    wl["star2d_dirichlet"] = Workload(
+        "star2d_dirichlet", 2, (8192, 8192), "f32", 1000, STAR,
+        to_f32_exact(star2d_weights(0.6, 0.1)), (1, 2, 4),
+        "2D 5-point star (0.6; 0.1 x4), 8192^2 FP32, T=1000, zero Dirichlet boundaries; "
+        "plain, fold m=2, m=4", {"boundary": "zero"})
     # the paper's worked example (Section 3.3): the unit 9-point box, here
     # normalised (each weight fl32(1/9)), whose folds are rank one
     wl["unitbox2d"] = Workload(

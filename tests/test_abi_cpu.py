@@ -65,10 +65,12 @@ def test_plan_create_rejects_nonfinite_and_off_axis_star():
     with pytest.raises(sf.StencilError) as e:
         sf.stencil_plan_create(2, 1, sf.STENCIL_STAR, w)
     assert e.value.code == sf.STENCIL_E_ARG
-    with pytest.raises(sf.StencilError) as e:
-        sf.stencil_plan_create(2, 1, sf.STENCIL_STAR, synth.star2d_weights(0.6, 0.1),
+    h = sf.stencil_plan_create(2, 1, sf.STENCIL_STAR, synth.star2d_weights(0.6, 0.1),
                                sf.STENCIL_DIRICHLET)
-    assert e.value.code == sf.STENCIL_E_UNSUPPORTED
+    sf.stencil_plan_destroy(h)
+    with pytest.raises(sf.StencilError) as e:
+        sf.stencil_plan_create(2, 1, sf.STENCIL_STAR, synth.star2d_weights(0.6, 0.1), 7)
+    assert e.value.code == sf.STENCIL_E_ARG
     rc = sf.lib.stencil_plan_create(2, 1, 0, None, 0, ctypes.byref(ctypes.c_void_p()))
     assert rc == sf.STENCIL_E_ARG
 
@@ -192,6 +194,11 @@ def test_run_schedule_counts_launches():
     w4 = synth.random_positive_weights(2, 4, mask=synth.star_mask(2, 4))
     s = _sched(sf.Plan(w4, sf.STENCIL_STAR), (8192, 8192), 1001)
     assert (s["plain_launches"], s["final_copy"]) == (502, False)
+    # zero-boundary plans: any axis >= 1, no fusion, always a copy back
+    dstar = sf.Plan(synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR, sf.STENCIL_DIRICHLET)
+    s = _sched(dstar, (8192, 8192), 16)
+    assert (s["plain_launches"], s["final_copy"]) == (16, True)
+    assert _sched(dstar, (1, 2), 3)["plain_launches"] == 3
     # boxes of radius 3 and more are not fused (FMA-issue bound already)
     b3 = synth.random_positive_weights(2, 3)
     assert _sched(sf.Plan(b3, sf.STENCIL_BOX), (8192, 8192), 10)["plain_launches"] == 10

@@ -168,3 +168,30 @@ def test_batched_full_size_sampled_grids(tmp_path):
         assert np.array_equal(datas[i].cpu().numpy(), ref), (i, int(sides[i]), chosen[i])
     for p in plans:
         p.close()
+
+
+def test_dirichlet_sampled_outputs_full_size():
+    """Zero boundaries at the measured size (8192^2, fold m = 4, T = 8):
+    sampled points, corners and edges included, against the FP64 zero-ghost
+    oracle on the point's window clipped to the grid (a window edge inside the
+    grid perturbs points within T*r of it only, so the centre is exact)."""
+    wl = synth.WORKLOADS["star2d_dirichlet"]
+    u0 = full_grid("star2d")
+    T, m = 8, 4
+    plan = sf.Plan(wl.weights, wl.shape_kind, sf.STENCIL_DIRICHLET)
+    plan.fold(m)
+    d = torch.from_numpy(u0).to(DEV)
+    plan.run(d, T)
+    torch.cuda.synchronize()
+    plan.close()
+    ny, nx = wl.shape
+    pts = sampled_points(wl.shape, 30, zlib.crc32(b"star2d_dirichlet"))
+    pts += [(0, nx // 2), (ny // 2, 0), (ny - 1, nx // 2), (2, nx - 3), (ny - 4, 1)]
+    reach = T * 1
+    for p in pts:
+        y0, y1 = max(0, p[0] - reach), min(ny, p[0] + reach + 1)
+        x0, x1 = max(0, p[1] - reach), min(nx, p[1] + reach + 1)
+        win = u0[y0:y1, x0:x1].astype(np.float64)
+        ref = oracle.sweep(wl.weights, win, T, "zero")[p[0] - y0, p[1] - x0]
+        got = d[p].item()
+        assert abs(got - ref) <= 1e-5 * abs(ref), (p, got, ref)

@@ -478,3 +478,92 @@ def test_separable_mode(case):
     assert oracle.errors(got, ref64)["e_rel"] < 1e-5
     if not used:
         assert np.array_equal(got, oracle.folded_reference_f32(w, u0, T, m))
+
+
+# ------------------------------------------------- zero Dirichlet boundaries
+
+DIR_CASES = [
+    # (name, weights, kind, shape, T, m, dtype)
+    ("heat1d_plain_f64", synth.heat1d_weights(), sf.STENCIL_STAR, (1000,), 7, 1, "f64"),
+    ("heat1d_m3_f32", synth.heat1d_weights(), sf.STENCIL_STAR, (37,), 10, 3, "f32"),
+    ("star2d_plain", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (100, 130), 9, 1, "f32"),
+    ("star2d_m4", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (64, 256), 13, 4, "f32"),
+    ("star2d_m2_f64", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (50, 61), 7, 2, "f64"),
+    ("box2d_m2", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (37, 41), 8, 2, "f32"),
+    ("box2d_m8", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (90, 300), 17, 8, "f32"),
+    ("tiny_band_everywhere", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (3, 5), 9, 4, "f32"),
+    ("one_row", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (1, 9), 5, 2, "f32"),
+    ("star3d_m2", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (12, 14, 18), 5, 2, "f32"),
+    ("box3d_plain", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (9, 10, 11), 3, 1, "f32"),
+]
+
+
+def _run_dirichlet(w, kind, u0, T, m, mode=sf.STENCIL_MODE_VECTOR, plan=None):
+    own = plan is None
+    if own:
+        plan = sf.Plan(w, kind, sf.STENCIL_DIRICHLET)
+        if m > 1:
+            plan.fold(m)
+        plan.set_mode(mode)
+    data = torch.from_numpy(np.ascontiguousarray(u0)).to(DEV)
+    plan.run(data, T)
+    torch.cuda.synchronize()
+    if own:
+        plan.close()
+    return data.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", DIR_CASES, ids=lambda c: c[0])
+def test_dirichlet_bit_exact_vs_mirror(case):
+    """Zero-boundary runs (folded interior, plain-stepped band, zero pad
+    restored per application) equal the oracle's mirror of the same reading
+    bit for bit (canonical-order kernels), and the FP64 zero-ghost sweep
+    within the FP32 gate."""
+    name, w, kind, shape, T, m, dt = case
+    print("dirichlet", name, shape, "T", T, "m", m, dt, flush=True)
+    if dt == "f32":
+        w = synth.to_f32_exact(w)
+        u0 = synth.grid_f32(shape)
+    else:
+        u0 = synth.grid_f64(shape)
+    got = _run_dirichlet(w, kind, u0, T, m)
+    ref64 = oracle.sweep(w, u0.astype(np.float64), T, "zero")
+    if dt == "f32":
+        assert np.array_equal(got, oracle.dirichlet_folded(w, u0, T, m, f32=True))
+        assert oracle.errors(got, ref64)["e_rel"] < 1e-5
+    else:
+        assert np.array_equal(got, oracle.dirichlet_folded(w, u0, T, m))
+        assert oracle.errors(got, ref64)["e_rel"] < 1e-13
+
+
+@pytest.mark.parametrize("mode,gate", [("exact", 0.0), ("symmetric", 1e-5), ("separable", 1e-5),
+                                       ("mfma", 1e-3)])
+def test_dirichlet_other_modes(mode, gate):
+    w = np.full((3, 3), 1.0 / 9.0) if mode == "separable" else synth.WORKLOADS["star2d"].weights
+    if mode == "mfma":
+        w = synth.WORKLOADS["box2d"].weights
+    w = synth.to_f32_exact(w)
+    kind = sf.STENCIL_STAR if mode in ("exact", "symmetric") else sf.STENCIL_BOX
+    code = {"exact": sf.STENCIL_MODE_EXACT_ORDER, "symmetric": sf.STENCIL_MODE_SYMMETRIC,
+            "separable": sf.STENCIL_MODE_SEPARABLE, "mfma": sf.STENCIL_MODE_MFMA_BF16X3}[mode]
+    u0 = synth.grid_f32((70, 256))
+    T, m = 11, 4
+    got = _run_dirichlet(w, kind, u0, T, m, code)
+    if gate == 0.0:
+        assert np.array_equal(got, oracle.dirichlet_folded(w, u0, T, m, f32=True))
+    else:
+        ref64 = oracle.sweep(w, u0.astype(np.float64), T, "zero")
+        assert oracle.errors(got, ref64)["e_rel"] < gate
+
+
+def test_dirichlet_plan_reused_across_geometries():
+    """The padded buffers are kept by the plan: a smaller grid after a larger
+    one (stale data where the new pads lie) and the larger one again."""
+    w = synth.WORKLOADS["star2d"].weights
+    plan = sf.Plan(w, sf.STENCIL_STAR, sf.STENCIL_DIRICHLET)
+    plan.fold(2)
+    for shape, T in (((64, 200), 7), ((20, 33), 6), ((64, 200), 5)):
+        u0 = synth.grid_f32(shape)
+        got = _run_dirichlet(w, sf.STENCIL_STAR, u0, T, 2, plan=plan)
+        assert np.array_equal(got, oracle.dirichlet_folded(w, u0, T, 2, f32=True)), shape
+    plan.close()
