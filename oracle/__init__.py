@@ -21,6 +21,8 @@ from .core import (  # noqa: F401
     folded_reference_f32,
     band_mask,
     dirichlet_folded,
+    floor_sweep,
+    life,
     errors,
     exact_sum,
     collect_counts,

@@ -281,6 +281,43 @@ def dirichlet_folded(w, u0, T: int, m: int, f32: bool = False) -> np.ndarray:
     return u
 
 
+def floor_sweep(w, u0, floor, T: int, f32: bool = False) -> np.ndarray:
+    """T steps of u <- max(A u, floor) (IEEE maxNum, elementwise): the
+    American put option pricing benchmark of Table 1 (APOP: a 1D 3-point
+    stencil over two arrays, the option value and its exercise payoff, whose
+    update keeps the larger).  Periodic, like the plain sweep.  The max
+    makes the update nonlinear, so it is never folded.  f32: the same steps
+    in FP32 (sweep_f32, then fmax), the bit-exact reference."""
+    if f32:
+        u = np.asarray(u0, dtype=np.float32)
+        fl = np.asarray(floor, dtype=np.float32)
+        w1 = np.asarray(w, dtype=np.float64).astype(np.float32)
+        step = sweep_f32
+    else:
+        u = np.asarray(u0, dtype=np.float64)
+        fl = np.asarray(floor, dtype=np.float64)
+        w1 = np.asarray(w, dtype=np.float64)
+        step = sweep
+    for _ in range(T):
+        u = np.fmax(step(w1, u, 1), fl)
+    return u
+
+
+def life(cells, T: int) -> np.ndarray:
+    """T generations of Conway's Game of Life (Table 1: each cell's update
+    depends on its 8 neighbours) on a periodic grid of 0/1 cells: a cell is
+    alive next iff it has exactly 3 live neighbours, or 2 and is alive."""
+    c = np.asarray(cells, dtype=np.uint8)
+    for _ in range(T):
+        n = np.zeros(c.shape, dtype=np.int32)
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dy or dx:
+                    n += np.roll(c, (dy, dx), axis=(0, 1))
+        c = ((n == 3) | ((c == 1) & (n == 2))).astype(np.uint8)
+    return c
+
+
 def exact_sum(u) -> float:
     """Correctly rounded sum of all values (math.fsum)."""
     return math.fsum(np.asarray(u, dtype=np.float64).ravel().tolist())

@@ -587,3 +587,70 @@ def test_dirichlet_mirror_f32_close_to_fp64():
     got = oracle.dirichlet_folded(w, u0, 9, 4, f32=True)
     ref = oracle.sweep(w, u0.astype(np.float64), 9, "zero")
     assert oracle.errors(got, ref)["e_rel"] < 1e-6
+
+
+# ------------------------------------------------- nonlinear Table 1 workloads
+
+def _life_brute(cells, T):
+    """Game of Life by explicit loops over cells and neighbours (tiny grids)."""
+    ny, nx = cells.shape
+    c = [[int(v) for v in row] for row in cells]
+    for _ in range(T):
+        nxt = [[0] * nx for _ in range(ny)]
+        for y in range(ny):
+            for x in range(nx):
+                k = sum(c[(y + dy) % ny][(x + dx) % nx]
+                        for dy in (-1, 0, 1) for dx in (-1, 0, 1) if dy or dx)
+                nxt[y][x] = 1 if (k == 3 or (k == 2 and c[y][x])) else 0
+        c = nxt
+    return np.array(c, dtype=np.uint8)
+
+
+def test_life_known_patterns():
+    g = np.zeros((8, 8), dtype=np.uint8)
+    g[3, 2:5] = 1  # blinker: period 2
+    assert np.array_equal(oracle.life(g, 2), g) and not np.array_equal(oracle.life(g, 1), g)
+    b = np.zeros((6, 6), dtype=np.uint8)
+    b[2:4, 2:4] = 1  # block: still life
+    assert np.array_equal(oracle.life(b, 5), b)
+    gl = np.zeros((10, 10), dtype=np.uint8)
+    for y, x in ((0, 1), (1, 2), (2, 0), (2, 1), (2, 2)):  # glider: (+1, +1) per 4
+        gl[y, x] = 1
+    assert np.array_equal(oracle.life(gl, 4), np.roll(gl, (1, 1), axis=(0, 1)))
+    assert np.array_equal(oracle.life(gl, 40), np.roll(gl, (10, 10), axis=(0, 1)))
+
+
+@pytest.mark.parametrize("shape", [(5, 7), (9, 4), (3, 3), (1, 6)])
+def test_life_brute_force(shape):
+    g = rng(sum(shape)).integers(0, 2, size=shape).astype(np.uint8)
+    assert np.array_equal(oracle.life(g, 6), _life_brute(g, 6))
+
+
+def test_floor_sweep_reduces_and_bounds():
+    """APOP reading: with a floor below every reachable value it is the plain
+    sweep; with dyadic weights summing to 1 and a constant floor above the
+    data every step lands exactly on the floor; the result never drops
+    below the floor nor below the plain sweep (positive weights)."""
+    w = np.array([0.25, 0.5, 0.25])
+    u0 = rng(3).random(64)
+    low = np.full(64, -10.0)
+    assert np.array_equal(oracle.floor_sweep(w, u0, low, 7), oracle.sweep(w, u0, 7))
+    high = np.full(64, 2.0)
+    assert np.array_equal(oracle.floor_sweep(w, u0, high, 3), high)
+    payoff = np.maximum(0.5 - np.arange(64) / 64.0, 0.0)
+    got = oracle.floor_sweep(w, u0, payoff, 9)
+    assert np.all(got >= payoff) and np.all(got >= oracle.sweep(w, u0, 9))
+
+
+def test_floor_sweep_rational_brute_force():
+    w = [Fraction(1, 5), Fraction(1, 2), Fraction(1, 4)]
+    g = rng(11)
+    n = 9
+    u = [Fraction(int(v), 8) for v in g.integers(0, 8, size=n)]
+    fl = [Fraction(int(v), 8) for v in g.integers(0, 6, size=n)]
+    ref = list(u)
+    for _ in range(4):
+        ref = [max(sum(w[o + 1] * ref[(i + o) % n] for o in (-1, 0, 1)), fl[i]) for i in range(n)]
+    got = oracle.floor_sweep(np.array([float(v) for v in w]), np.array([float(v) for v in u]),
+                             np.array([float(v) for v in fl]), 4)
+    assert np.max(np.abs(got - np.array([float(v) for v in ref]))) < 16 * EPS64
