@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="star2d",
                     choices=["star2d", "heat1d", "star3d", "box3d", "box2d", "unitbox2d",
-                             "star2d_dirichlet", "batched"])
+                             "star2d_dirichlet", "box1d5p", "apop1d", "life2d", "batched"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only-m", type=int, default=0,
@@ -483,6 +483,137 @@ def bench_batched(args):
     return res
 
 
+def bench_apop(args):
+    """Table 1's APOP: N = 10,240,000 option values (FP64), T = 1000 steps of
+    u <- maxNum(A u, payoff) with a 3-point discounted stencil, several steps
+    fused per launch.  Algorithmic bytes per launch: the values read and
+    written once and the payoff read once (24 per point)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2103_09235_amd as sf
+    n, T, w = synth.APOP["n"], synth.APOP["T"], synth.APOP["weights"]
+    payoff = synth.apop_payoff(n)
+    dev = torch.device("cuda:0")
+    fl = torch.from_numpy(payoff).to(dev)
+    data = torch.from_numpy(payoff.copy()).to(dev)
+    scratch = torch.empty_like(data)
+    plan = sf.Plan(w, sf.STENCIL_STAR)
+    plan.set_floor(fl)
+    sched = plan.schedule(data, T, scratch)
+    log("[bench] apop1d: N=%d FP64 T=%d, %s" % (n, T, sched))
+    el, wall = time_runs(lambda: plan.run(data, T, scratch), args.steps, args.warmup)
+    gst = n * T * args.steps / el / 1e9
+    launches = sched["plain_launches"]
+    launch_ms = el / args.steps / launches * 1e3
+    algo = 24 * n
+    # correctness of one run: sampled points against the oracle's FP64 loop on
+    # each point's window (T*r on each side: a window edge perturbs points
+    # within T*r of it only, so the centre is exact), bit for bit
+    import oracle
+    data.copy_(torch.from_numpy(payoff).to(dev))
+    plan.run(data, T, scratch)
+    u = data.cpu().numpy()
+    plan.close()
+    ok = True
+    for x in (0, 1, 12345, n // 3, n // 2, n - 2, n - 1):
+        idx = (x + np.arange(-T, T + 1)) % n
+        ref = oracle.floor_sweep(w, payoff[idx], payoff[idx], T)[T]
+        ok = ok and bool(u[x] == ref)
+    # per step and point: 3 FMAs and a max (counted as 2 x 3 flops)
+    flops = 2 * 3 * n * (T / launches)
+    dur = launch_ms / 1e3
+    if flops / algo < FP64_VECTOR_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
+        roof = {"bound": "hbm", "achieved": round(algo / dur / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": round(flops / dur / 1e12, 2),
+                "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "peak_basis": "FP64 vector, published"}
+    roof.update({"kernel": "k_sweep1d<double, 1, 16, floor> (%.1f steps per launch)" % (
+                     T / launches),
+                 "launch_ms": round(launch_ms, 5), "algorithmic_bytes_per_launch": algo,
+                 "algorithmic_flops_per_launch": flops, "hbm_frac": round(
+                     algo / dur / 1e9 / HBM_PEAK_GBS, 4), "traffic": None})
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    res = {"metric": METRIC, "value": round(gst, 2), "unit": "GStencil/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(el / args.steps * 1e3, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "APOP (Table 1): 1D 3-point discounted stencil floored by the "
+                                  "put payoff, N=10,240,000 FP64, T=1000, plain (not foldable)",
+                      "points": n, "T": T},
+           "roofline": roof, "sampled_points_match_oracle": ok, "wall_s": round(wall, 3)}
+    if not args.no_cpu:
+        m = 1 << 20
+        oracle.floor_sweep(w, payoff[:m], payoff[:m], 1)
+        t0 = time.perf_counter()
+        oracle.floor_sweep(w, payoff[:m], payoff[:m], 2)
+        per = (time.perf_counter() - t0) / 2
+        Ts = int(max(1, min(T, args.cpu_seconds / per)))
+        t0 = time.perf_counter()
+        oracle.floor_sweep(w, payoff[:m], payoff[:m], Ts)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(m * Ts / dt / 1e9, 4), "unit": "GStencil/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": "FP64 floor sweep on the first %d points (periodic), "
+                                         "%d of the %d steps, %.1f s" % (m, Ts, T, dt)}
+    return res
+
+
+def bench_life(args):
+    """Table 1's Game of Life: 5000 x 5000 cells (uint8), T = 1000
+    generations, one generation per launch; 2 algorithmic bytes per cell per
+    generation (read and write once)."""
+    import numpy as np
+    import torch
+    import synth
+    import oracle
+    import paper_2103_09235_amd as sf
+    shape, T = synth.LIFE["shape"], synth.LIFE["T"]
+    g0 = synth.life_cells(shape)
+    dev = torch.device("cuda:0")
+    cells = torch.from_numpy(g0).to(dev)
+    scratch = torch.empty_like(cells)
+    n = int(np.prod(shape))
+    log("[bench] life2d: %s T=%d" % (shape, T))
+    el, wall = time_runs(lambda: sf.stencil_life(cells, scratch, T), args.steps, args.warmup)
+    gst = n * T * args.steps / el / 1e9
+    launch_ms = el / args.steps / T * 1e3
+    # correctness: 4 generations against the oracle
+    cells.copy_(torch.from_numpy(g0).to(dev))
+    sf.stencil_life(cells, scratch, 4)
+    ok = bool(np.array_equal(cells.cpu().numpy(), oracle.life(g0, 4)))
+    roof = {"bound": "hbm", "achieved": round(2 * n / (launch_ms / 1e3) / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "kernel": "k_life4 (4 cells per thread)",
+            "launch_ms": round(launch_ms, 5), "algorithmic_bytes_per_launch": 2 * n,
+            "traffic": None}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    res = {"metric": METRIC, "value": round(gst, 2), "unit": "GStencil/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(el / args.steps * 1e3, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "Game of Life (Table 1), 5000x5000 uint8 cells, periodic, "
+                                  "T=1000 generations, plain (not foldable)",
+                      "points": n, "T": T},
+           "roofline": roof, "matches_oracle_4_generations": ok, "wall_s": round(wall, 3)}
+    if not args.no_cpu:
+        sample = g0[:1000, :1000]
+        oracle.life(sample, 1)
+        t0 = time.perf_counter()
+        oracle.life(sample, 2)
+        per = (time.perf_counter() - t0) / 2
+        Ts = int(max(1, min(T, args.cpu_seconds / per)))
+        t0 = time.perf_counter()
+        oracle.life(sample, Ts)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(sample.size * Ts / dt / 1e9, 4),
+                               "unit": "GStencil/s", "cores": 1, "kind": "oracle",
+                               "sample": "numpy Game of Life on a 1000x1000 corner, %d of the "
+                                         "%d generations, %.1f s" % (Ts, T, dt)}
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -507,6 +638,10 @@ def main():
         return
     if args.workload == "batched":
         res = bench_batched(args)
+    elif args.workload == "apop1d":
+        res = bench_apop(args)
+    elif args.workload == "life2d":
+        res = bench_life(args)
     else:
         res = bench_grid(args, args.workload)
     print(json.dumps(res), flush=True)

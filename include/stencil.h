@@ -171,6 +171,35 @@ int stencil_plan_set_fusion(stencil_plan p, int max_steps);
 int stencil_plan_separable(stencil_plan p, int *rank, int *applies);
 
 /*
+ * stencil_plan_set_floor -- an obstacle applied after every step:
+ * u_{t+1} = maxNum(A u_t, floor), elementwise (the American put option
+ * pricing benchmark of Table 1, APOP: a 1D 3-point stencil over two arrays,
+ * the option value and its exercise payoff, keeping the larger).
+ *   floor  device, caller-owned, count elements of dtype, read by every run
+ *          of this plan until replaced; NULL removes the floor.
+ * The update is no longer linear: runs need fold depth 1 and VECTOR mode
+ * (else E_UNSUPPORTED), a grid of the floor's dtype and count (else E_ARG).
+ * Steps are still fused several per launch (the floor values of a lane stay
+ * in registers); each step is the canonical chain followed by the max.
+ * Errors: E_ARG; E_UNSUPPORTED unless the plan is 1D, radius <= 8, periodic.
+ * No device work.
+ */
+int stencil_plan_set_floor(stencil_plan p, const void *floor, int dtype, int64_t count);
+
+/*
+ * stencil_life -- T generations of Conway's Game of Life (Table 1: a cell's
+ * update depends on its 8 neighbours) on a periodic ny x nx grid of uint8
+ * cells, 0 dead and 1 alive (other values are not allowed): a cell is alive
+ * in the next generation iff it has exactly 3 live neighbours, or 2 and is
+ * alive.  Not linear, so never folded.
+ *   cells    device, caller-owned, row-major (x fastest); the result lands here.
+ *   scratch  device, caller-owned, ny*nx bytes, not overlapping cells.
+ *   stream   hipStream_t or NULL.  Asynchronous; T = 0 is a no-op.
+ * Errors: E_ARG, E_UNSUPPORTED (grid too large), E_DEVICE.
+ */
+int stencil_life(void *cells, void *scratch, int64_t ny, int64_t nx, int64_t T, void *stream);
+
+/*
  * stencil_plan_info -- read back plan parameters (any pointer may be NULL):
  * dimension, radius r, fold depth m, folded radius m*r, mode.
  */

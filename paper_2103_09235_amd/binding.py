@@ -32,6 +32,7 @@ STENCIL_E_STATE = -5
 EXPORTS = (
     "stencil_plan_create", "stencil_fold_weights", "stencil_fold_weights_f32",
     "stencil_plan_set_mode", "stencil_plan_set_fusion", "stencil_plan_separable",
+    "stencil_plan_set_floor", "stencil_life",
     "stencil_plan_info",
     "stencil_profitability", "stencil_run", "stencil_run_schedule", "stencil_run_batched", "stencil_residual",
     "stencil_plan_destroy", "stencil_last_error", "stencil_version",
@@ -88,6 +89,8 @@ def _load() -> ctypes.CDLL:
     lib.stencil_plan_set_mode.argtypes = [P, ctypes.c_int]
     lib.stencil_plan_set_fusion.argtypes = [P, ctypes.c_int]
     lib.stencil_plan_separable.argtypes = [P, ip, ip]
+    lib.stencil_plan_set_floor.argtypes = [P, P, ctypes.c_int, ctypes.c_int64]
+    lib.stencil_life.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, P]
     lib.stencil_plan_info.argtypes = [P, ip, ip, ip, ip, ip]
     lib.stencil_profitability.argtypes = [P, ctypes.c_int, i64p, i64p]
     lib.stencil_run.argtypes = [P, ctypes.POINTER(stencil_grid), ctypes.c_int64]
@@ -164,6 +167,31 @@ def stencil_plan_separable(plan):
     rank, applies = ctypes.c_int(), ctypes.c_int()
     _check(lib.stencil_plan_separable(plan, ctypes.byref(rank), ctypes.byref(applies)))
     return rank.value, bool(applies.value)
+
+
+def stencil_plan_set_floor(plan, floor) -> None:
+    """Attach a device tensor as the plan's floor (None removes it).  The
+    caller keeps the tensor alive while the plan may run."""
+    if floor is None:
+        _check(lib.stencil_plan_set_floor(plan, None, 0, 0))
+        return
+    if not floor.is_cuda or not floor.is_contiguous():
+        raise StencilError(STENCIL_E_ARG, "floor must be a contiguous device tensor")
+    _check(lib.stencil_plan_set_floor(plan, floor.data_ptr(), _dtype_code(floor), floor.numel()))
+
+
+def stencil_life(cells, scratch, T: int, stream=None) -> None:
+    """T generations of the Game of Life on a 2D uint8 device tensor."""
+    import torch
+    if cells.dtype != torch.uint8 or cells.dim() != 2 or not cells.is_contiguous():
+        raise StencilError(STENCIL_E_ARG, "cells must be a contiguous 2D uint8 device tensor")
+    if scratch.shape != cells.shape or scratch.dtype != torch.uint8:
+        raise StencilError(STENCIL_E_ARG, "scratch must match cells")
+    if stream is None:
+        stream = torch.cuda.current_stream(cells.device)
+    st = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(lib.stencil_life(cells.data_ptr(), scratch.data_ptr(), cells.shape[0], cells.shape[1],
+                            int(T), st))
 
 
 def stencil_plan_info(plan) -> dict:
@@ -299,6 +327,10 @@ class Plan:
 
     def separable(self):
         return stencil_plan_separable(self.handle)
+
+    def set_floor(self, floor) -> None:
+        stencil_plan_set_floor(self.handle, floor)
+        self._floor = floor  # keeps the tensor alive with the plan
 
     def info(self) -> dict:
         return stencil_plan_info(self.handle)

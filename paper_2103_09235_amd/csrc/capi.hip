@@ -198,7 +198,8 @@ hipError_t dispatch(stencil_plan p, const SweepLaunch &L) {
   }
   else e = launch_sweep3d(L);
   if (e == hipErrorNotSupported) {
-    if (L.steps != 1) return hipErrorNotSupported;
+    // the generic kernel neither fuses steps nor applies a floor
+    if (L.steps != 1 || L.floor) return hipErrorNotSupported;
     (void)hipGetLastError();
     e = launch_naive(L);
   }
@@ -356,6 +357,55 @@ int stencil_plan_separable(stencil_plan p, int *rank, int *applies) {
   return STENCIL_OK;
 }
 
+int stencil_plan_set_floor(stencil_plan p, const void *floor, int dtype, int64_t count) {
+  set_error("");
+  if (int rc = check_plan(p)) return rc;
+  if (!floor) {
+    p->floor = nullptr;
+    p->floor_count = 0;
+    return STENCIL_OK;
+  }
+  if (dtype != STENCIL_F32 && dtype != STENCIL_F64)
+    return fail(STENCIL_E_ARG, "dtype must be STENCIL_F32 or STENCIL_F64");
+  if (count < 1) return fail(STENCIL_E_ARG, "count must be >= 1");
+  if (p->dim != 1 || p->r > 8)
+    return fail(STENCIL_E_UNSUPPORTED, "a floor needs a 1D plan of radius <= 8");
+  if (p->boundary != STENCIL_PERIODIC)
+    return fail(STENCIL_E_UNSUPPORTED, "a floor needs periodic boundaries");
+  p->floor = floor;
+  p->floor_dtype = dtype;
+  p->floor_count = count;
+  return STENCIL_OK;
+}
+
+int stencil_life(void *cells, void *scratch, int64_t ny, int64_t nx, int64_t T, void *stream) {
+  set_error("");
+  if (!cells || !scratch) return fail(STENCIL_E_ARG, "cells and scratch must be non-NULL");
+  if (ny < 1 || nx < 1) return fail(STENCIL_E_ARG, "ny and nx must be >= 1");
+  if (T < 0) return fail(STENCIL_E_ARG, "T must be >= 0");
+  if (ny > ((int64_t)1 << 30) || nx > ((int64_t)1 << 30) || ny * nx > ((int64_t)1 << 40))
+    return fail(STENCIL_E_UNSUPPORTED, "grid too large");
+  const int64_t bytes = ny * nx;
+  const char *a = (const char *)cells, *b = (const char *)scratch;
+  if (a < b + bytes && b < a + bytes) return fail(STENCIL_E_ARG, "cells and scratch overlap");
+  if (T == 0) return STENCIL_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const uint8_t *src = (const uint8_t *)cells;
+  uint8_t *dst = (uint8_t *)scratch;
+  for (int64_t t = 0; t < T; ++t) {
+    hipError_t e = launch_life(src, dst, ny, nx, s);
+    if (e != hipSuccess) return hip_fail(e, "life generation");
+    const uint8_t *o = src;
+    src = dst;
+    dst = const_cast<uint8_t *>(o);
+  }
+  if (src != cells) {
+    hipError_t e = launch_copy(src, cells, bytes, s);
+    if (e != hipSuccess) return hip_fail(e, "final copy");
+  }
+  return STENCIL_OK;
+}
+
 int stencil_plan_set_fusion(stencil_plan p, int max_steps) {
   set_error("");
   if (int rc = check_plan(p)) return rc;
@@ -423,6 +473,14 @@ int check_run(stencil_plan p, const stencil_grid *g, int64_t T, Geom &geo) {
       return fail(STENCIL_E_UNSUPPORTED,
                   "every grid axis must be >= 2*m*r+1 for this plan");
   if (geo.count() > ((int64_t)1 << 40)) return fail(STENCIL_E_UNSUPPORTED, "grid too large");
+  if (p->floor) {
+    if (p->m != 1)
+      return fail(STENCIL_E_UNSUPPORTED, "a floor makes the update nonlinear: fold depth must be 1");
+    if (p->mode != STENCIL_MODE_VECTOR)
+      return fail(STENCIL_E_UNSUPPORTED, "a floor runs in VECTOR mode only");
+    if (g->dtype != p->floor_dtype || geo.count() != p->floor_count)
+      return fail(STENCIL_E_ARG, "the floor must have the grid's dtype and point count");
+  }
   const size_t bytes = (size_t)geo.count() * esize(g->dtype);
   if (g->scratch) {
     const char *a = (const char *)g->data, *b = (const char *)g->scratch;
@@ -620,6 +678,7 @@ int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
   L.g = geo;
   L.dtype = g->dtype;
   L.stream = (hipStream_t)g->stream;
+  L.floor = p->floor;
   const void *src = g->data;
   void *dst = scratch;
   for (int i = 0; i < 2; ++i) {

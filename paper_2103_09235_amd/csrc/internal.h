@@ -75,6 +75,9 @@ struct DeviceState {
 struct stencil_plan_s {
   int dim = 0, r = 0, shape = 0, boundary = 0, mode = STENCIL_MODE_VECTOR;
   int max_fuse = 0;           // steps one launch may fuse; 0 = library choice
+  const void *floor = nullptr;  // caller's floor array (device), or none
+  int floor_dtype = 0;
+  int64_t floor_count = 0;
   std::vector<double> w;      // plain weights, FP64, (2r+1)^dim
   int m = 1;                  // fold depth
   std::vector<double> Wm;     // folded FP64 weights, (2mr+1)^dim
@@ -118,6 +121,7 @@ struct SweepLaunch {
   int steps = 1;       // operator applications fused into this launch
   bool sym = false;    // mode SYMMETRIC: share mirrored partial sums if the operator allows
   bool sep = false;    // mode SEPARABLE: low-rank form if the operator has one
+  const void *floor = nullptr;  // 1D: u = maxNum(u, floor) after every step
   hipStream_t stream = nullptr;
 };
 
@@ -133,6 +137,8 @@ hipError_t launch_sweep3d(const SweepLaunch &L);
 hipError_t launch_mfma2d(const SweepLaunch &L);
 // Host-built B-fragment table the matrix-core kernel loads per lane.
 std::vector<uint16_t> mfma_b_table(const std::vector<float> &w, int R);
+// Game of Life generations on a periodic uint8 grid (life.hip).
+hipError_t launch_life(const uint8_t *in, uint8_t *out, int64_t ny, int64_t nx, hipStream_t s);
 // Largest number of fused steps the 1D kernel takes per launch.
 int sweep1d_max_steps(const SweepLaunch &L);
 // 2D FP32 temporal blocking: the most steps one launch fuses (1 = none), and

@@ -17,6 +17,10 @@
 // Every step of every point is the plain update in canonical order
 // (acc = +0, one FMA per tap, offsets ascending), so results are
 // bit-identical to k separate sweeps.
+//
+// With a floor array (the APOP benchmark of Table 1: option values never
+// drop below the exercise payoff) every step ends with u = maxNum(u, floor)
+// at each point; the lane keeps its points' floor values in registers.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -35,10 +39,13 @@ struct WArr1 {
 __device__ __forceinline__ float fma1(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma1(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-template <typename T, int R, int VX>
+__device__ __forceinline__ float max1(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double max1(double a, double b) { return __builtin_fmax(a, b); }
+
+template <typename T, int R, int VX, bool FLOOR>
 __global__ void __launch_bounds__(kThreads)
 k_sweep1d(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
-          int64_t span_out, WArr1<T, 2 * R + 1> W) {
+          int64_t span_out, WArr1<T, 2 * R + 1> W, const T *__restrict__ floor) {
   static_assert(VX >= R, "neighbour values must come from the adjacent lane");
   __shared__ T edge[2][2][kThreads][R];  // [buffer][left/right][lane][i]
   const int t = threadIdx.x;
@@ -46,12 +53,13 @@ k_sweep1d(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
   const int64_t halo = (int64_t)k * R;
   const int64_t base = out0 - halo + (int64_t)t * VX;    // first point of this lane
 
-  T cur[VX];
+  T cur[VX], fl[VX];
 #pragma unroll
   for (int v = 0; v < VX; ++v) {
     int64_t g = (base + v) % n;
     if (g < 0) g += n;
     cur[v] = in[g];
+    if constexpr (FLOOR) fl[v] = floor[g];
   }
 
   for (int s = 0; s < k; ++s) {
@@ -80,7 +88,7 @@ k_sweep1d(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
         const T x = p < 0 ? lnb[R + p] : (p >= VX ? rnb[p - VX] : cur[p]);
         acc = fma1(W.v[o + R], x, acc);
       }
-      nxt[v] = acc;
+      nxt[v] = FLOOR ? max1(acc, fl[v]) : acc;
     }
 #pragma unroll
     for (int v = 0; v < VX; ++v) cur[v] = nxt[v];
@@ -112,8 +120,14 @@ hipError_t launch_r(const SweepLaunch &L, const std::vector<T> &w) {
   const int64_t n = L.g.nx;
   const int64_t blocks = (n + span_out - 1) / span_out;
   if (blocks > (1LL << 31) - 1) return hipErrorNotSupported;
-  hipLaunchKernelGGL((k_sweep1d<T, R, VX>), dim3((unsigned)blocks), dim3(kThreads), 0,
-                     L.stream, (const T *)L.in, (T *)L.out, n, L.steps, span_out, W);
+  if (L.floor)
+    hipLaunchKernelGGL((k_sweep1d<T, R, VX, true>), dim3((unsigned)blocks), dim3(kThreads), 0,
+                       L.stream, (const T *)L.in, (T *)L.out, n, L.steps, span_out, W,
+                       (const T *)L.floor);
+  else
+    hipLaunchKernelGGL((k_sweep1d<T, R, VX, false>), dim3((unsigned)blocks), dim3(kThreads), 0,
+                       L.stream, (const T *)L.in, (T *)L.out, n, L.steps, span_out, W,
+                       (const T *)nullptr);
   return hipGetLastError();
 }
 

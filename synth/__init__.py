@@ -28,4 +28,8 @@ from .workloads import (  # noqa: F401
     star_mask,
     STAR,
     BOX,
+    APOP,
+    LIFE,
+    apop_payoff,
+    life_cells,
 )

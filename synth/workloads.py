@@ -139,6 +139,11 @@ def _make_workloads(seed: int = SEED) -> dict:
         to_f32_exact(random_positive_weights(2, 1, seed, STREAM_WEIGHTS)), (1, 4, 8),
         "2D 9-point random positive box, 16384^2 FP32, T=400; plain, fold m=4 "
         "(9x9) and m=8 (17x17), vector and BF16x3 MFMA")
+    # Table 1: 1D5P (a 5-point 1D box, radius 2), 10,240,000 points x 1000
+    wl["box1d5p"] = Workload(
+        "box1d5p", 1, (10_240_000,), "f64", 1000, BOX,
+        random_positive_weights(1, 2, seed, STREAM_WEIGHTS, offset=64), (1,),
+        "1D 5-point random positive box (1D5P), N=10,240,000, FP64, T=1000, plain sweep")
     # the star2d workload with zero Dirichlet boundaries (the paper states no
     # boundary; zero ghosts are the reading measured beside the periodic one)
     wl["star2d_dirichlet"] = Workload(
@@ -157,6 +162,23 @@ def _make_workloads(seed: int = SEED) -> dict:
 
 
 WORKLOADS = _make_workloads()
+
+# Table 1's nonlinear benchmarks (plain only: a max or a counting rule
+# cannot be folded).  APOP: option values over N asset prices, 3-point
+# stencil with a discount (weights sum 0.999), floored by the put payoff
+# max(0.6 - x/N, 0), starting from the payoff.  Game of Life: 5000^2 cells,
+# each alive with probability 1/2.
+APOP = dict(n=10_240_000, T=1000, weights=np.array([0.3, 0.45, 0.249]))
+LIFE = dict(shape=(5000, 5000), T=1000)
+
+
+def apop_payoff(n: int) -> np.ndarray:
+    return np.maximum(0.6 - np.arange(n, dtype=np.float64) / n, 0.0)
+
+
+def life_cells(shape, seed: int = SEED) -> np.ndarray:
+    u = uniform_f64(seed, STREAM_GRID, int(np.prod(shape)))
+    return (u < 0.5).astype(np.uint8).reshape(shape)
 
 
 def batched_recipe(count: int = 4096, seed: int = SEED, lo: int = 64, hi: int = 1024):

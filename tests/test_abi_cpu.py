@@ -245,3 +245,30 @@ def test_separable_rank_and_mode():
     # SEPARABLE runs one application per launch
     s = sf.stencil_run_schedule(unit.handle, (1024, 1024), sf.STENCIL_F32, 16, 1 << 20)
     assert s["plain_launches"] == 16
+
+
+def test_floor_and_life_validation():
+    p2 = sf.Plan(np.ones((3, 3)) / 9, sf.STENCIL_BOX)
+    assert sf.lib.stencil_plan_set_floor(p2.handle, 4096, sf.STENCIL_F32, 16) == \
+        sf.STENCIL_E_UNSUPPORTED
+    p1 = sf.Plan(synth.heat1d_weights(), sf.STENCIL_STAR)
+    assert sf.lib.stencil_plan_set_floor(p1.handle, 4096, 9, 16) == sf.STENCIL_E_ARG
+    assert sf.lib.stencil_plan_set_floor(p1.handle, 4096, sf.STENCIL_F64, 0) == sf.STENCIL_E_ARG
+    assert sf.lib.stencil_plan_set_floor(p1.handle, 4096, sf.STENCIL_F64, 16) == sf.STENCIL_OK
+    # the floor must match the grid; and it makes folding unavailable
+    g = sf.stencil_grid()
+    g.data = 1 << 20
+    g.dtype = sf.STENCIL_F64
+    g.dim = 1
+    g.shape[0] = 32
+    assert sf.lib.stencil_run(p1.handle, ctypes.byref(g), 3) == sf.STENCIL_E_ARG
+    p1.set_mode(sf.STENCIL_MODE_EXACT_ORDER)
+    g.shape[0] = 16
+    assert sf.lib.stencil_run(p1.handle, ctypes.byref(g), 3) == sf.STENCIL_E_UNSUPPORTED
+    assert sf.lib.stencil_plan_set_floor(p1.handle, None, 0, 0) == sf.STENCIL_OK
+    L = sf.lib.stencil_life
+    assert L(None, 4096, 8, 8, 1, None) == sf.STENCIL_E_ARG
+    assert L(1 << 20, 1 << 21, 0, 8, 1, None) == sf.STENCIL_E_ARG
+    assert L(1 << 20, 1 << 21, 8, 8, -1, None) == sf.STENCIL_E_ARG
+    assert L(1 << 20, (1 << 20) + 8, 8, 8, 1, None) == sf.STENCIL_E_ARG  # overlap
+    assert L(1 << 20, 1 << 21, 8, 8, 0, None) == sf.STENCIL_OK

@@ -195,3 +195,24 @@ def test_dirichlet_sampled_outputs_full_size():
         ref = oracle.sweep(wl.weights, win, T, "zero")[p[0] - y0, p[1] - x0]
         got = d[p].item()
         assert abs(got - ref) <= 1e-5 * abs(ref), (p, got, ref)
+
+
+def test_apop_full_size_sampled_bit_exact():
+    """APOP at its Table 1 size (10,240,000 points, FP64), 40 steps fused as
+    the library runs them: sampled points bit-exact against the oracle's loop
+    on each point's window."""
+    n, w = synth.APOP["n"], synth.APOP["weights"]
+    T = 40
+    payoff = synth.apop_payoff(n)
+    plan = sf.Plan(w, sf.STENCIL_STAR)
+    fl = torch.from_numpy(payoff).to(DEV)
+    plan.set_floor(fl)
+    d = torch.from_numpy(payoff.copy()).to(DEV)
+    plan.run(d, T, torch.empty_like(d))
+    torch.cuda.synchronize()
+    u = d.cpu().numpy()
+    plan.close()
+    for x in sampled_points((n,), 20, 7) :
+        x = x[0]
+        idx = (x + np.arange(-T, T + 1)) % n
+        assert u[x] == oracle.floor_sweep(w, payoff[idx], payoff[idx], T)[T], x

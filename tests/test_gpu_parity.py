@@ -567,3 +567,52 @@ def test_dirichlet_plan_reused_across_geometries():
         got = _run_dirichlet(w, sf.STENCIL_STAR, u0, T, 2, plan=plan)
         assert np.array_equal(got, oracle.dirichlet_folded(w, u0, T, 2, f32=True)), shape
     plan.close()
+
+
+# ------------------------------------------ nonlinear Table 1 workloads
+
+def _apop_inputs(n, f32):
+    u0 = synth.grid_f32((n,)) if f32 else synth.grid_f64((n,))
+    x = np.arange(n, dtype=np.float64)
+    payoff = np.maximum(0.6 - x / n, 0.0)
+    return u0, payoff.astype(np.float32) if f32 else payoff
+
+
+@pytest.mark.parametrize("n,T,f32,fusion", [(100_003, 37, False, 0), (37, 9, True, 0),
+                                            (4099, 64, True, 0), (4099, 12, False, 1)])
+def test_apop_floor_bit_exact(n, T, f32, fusion):
+    """u <- maxNum(A u, payoff) every step (APOP, Table 1), several steps
+    fused per launch: bit-exact against the oracle's step-by-step loop."""
+    w = synth.to_f32_exact(np.array([0.3, 0.45, 0.249])) if f32 else np.array([0.3, 0.45, 0.249])
+    u0, payoff = _apop_inputs(n, f32)
+    plan = sf.Plan(w, sf.STENCIL_STAR)
+    plan.set_fusion(fusion)
+    fl = torch.from_numpy(payoff).to(DEV)
+    plan.set_floor(fl)
+    data = torch.from_numpy(u0).to(DEV)
+    print("apop", n, T, f32, plan.schedule(data, T), flush=True)
+    plan.run(data, T, torch.empty_like(data))
+    torch.cuda.synchronize()
+    got = data.cpu().numpy()
+    plan.close()
+    assert np.array_equal(got, oracle.floor_sweep(w, u0, payoff, T, f32=f32))
+
+
+@pytest.mark.parametrize("shape,T", [((64, 96), 9), ((37, 41), 6), ((5000, 5000), 3),
+                                     ((3, 4), 5), ((1, 8), 2)])
+def test_life_bit_exact(shape, T):
+    g = np.random.default_rng(shape[0] * 7 + shape[1]).integers(0, 2, size=shape).astype(np.uint8)
+    cells = torch.from_numpy(g).to(DEV)
+    sf.stencil_life(cells, torch.empty_like(cells), T)
+    torch.cuda.synchronize()
+    assert np.array_equal(cells.cpu().numpy(), oracle.life(g, T))
+
+
+def test_life_glider_on_gpu():
+    g = np.zeros((32, 32), dtype=np.uint8)
+    for y, x in ((0, 1), (1, 2), (2, 0), (2, 1), (2, 2)):
+        g[y, x] = 1
+    cells = torch.from_numpy(g).to(DEV)
+    sf.stencil_life(cells, torch.empty_like(cells), 64)
+    torch.cuda.synchronize()
+    assert np.array_equal(cells.cpu().numpy(), np.roll(g, (16, 16), axis=(0, 1)))
