@@ -43,6 +43,11 @@ FP32_FMA_BASIS = ("FP32 FMA issue rate without packed FP32: 256 CUs x 64 lanes x
 FP64_VECTOR_TFLOPS = 78.6       # MI355X FP64 vector, published
 BF16_MFMA_TFLOPS = 2500.0       # MI355X dense BF16 matrix, published
 METRIC = "GStencil/s and % HBM roofline, plain vs folded/MFMA/batched at stated error"
+VALU32_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit VALU lane-operations per second (x1e12)
+# fused Game of Life: VALU instructions per wavefront row (64 words of 4
+# cells) and generation, 15.6-16.1 in the gfx950 assembly of the loop (16
+# and 4 generations per launch)
+LIFE_VALU_PER_ROW_GEN = 16.0
 
 
 def log(*a):
@@ -579,15 +584,24 @@ def bench_life(args):
     log("[bench] life2d: %s T=%d" % (shape, T))
     el, wall = time_runs(lambda: sf.stencil_life(cells, scratch, T), args.steps, args.warmup)
     gst = n * T * args.steps / el / 1e9
-    launch_ms = el / args.steps / T * 1e3
+    launches = sf.stencil_life_launches(shape[0], shape[1], T)
+    launch_ms = el / args.steps / launches * 1e3
     # correctness: 4 generations against the oracle
     cells.copy_(torch.from_numpy(g0).to(dev))
     sf.stencil_life(cells, scratch, 4)
     ok = bool(np.array_equal(cells.cpu().numpy(), oracle.life(g0, 4)))
-    roof = {"bound": "hbm", "achieved": round(2 * n / (launch_ms / 1e3) / 1e9, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "kernel": "k_life4 (4 cells per thread)",
+    # Integer VALU work: each lane (one 4-cell word) executes about
+    # LIFE_VALU_PER_ROW_GEN instructions per generation, priced against the
+    # 32-bit VALU issue rate (useful cells only, not the strips' borders).
+    gens = T / launches
+    dur = launch_ms / 1e3
+    ops = LIFE_VALU_PER_ROW_GEN * (n / 4) * gens  # lane-operations
+    roof = {"bound": "alu", "achieved": round(ops / dur / 1e12, 2),
+            "peak": VALU32_TOPS, "unit": "Tlane-op/s",
+            "peak_basis": "32-bit VALU issue: 256 CUs x 64 lanes x 2.4 GHz",
+            "kernel": "k_life_tb (%.2f generations per launch)" % gens,
             "launch_ms": round(launch_ms, 5), "algorithmic_bytes_per_launch": 2 * n,
-            "traffic": None}
+            "hbm_frac": round(2 * n / dur / 1e9 / HBM_PEAK_GBS, 4), "traffic": None}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
     res = {"metric": METRIC, "value": round(gst, 2), "unit": "GStencil/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,

@@ -195,9 +195,21 @@ int stencil_plan_set_floor(stencil_plan p, const void *floor, int dtype, int64_t
  *   cells    device, caller-owned, row-major (x fastest); the result lands here.
  *   scratch  device, caller-owned, ny*nx bytes, not overlapping cells.
  *   stream   hipStream_t or NULL.  Asynchronous; T = 0 is a no-op.
+ * Several generations run per launch where the grid allows (a wavefront
+ * streams a strip through one pipeline stage per generation), with the same
+ * result as one launch per generation.
  * Errors: E_ARG, E_UNSUPPORTED (grid too large), E_DEVICE.
  */
 int stencil_life(void *cells, void *scratch, int64_t ny, int64_t nx, int64_t T, void *stream);
+
+/*
+ * stencil_life_launches -- the number of kernel launches stencil_life makes
+ * for T generations on an ny x nx grid with 4-byte aligned buffers (grids
+ * whose rows are whole 4-cell words, at least 256 cells wide and 33 rows
+ * tall, run 16, 8, 4 or 2 generations per launch), not counting the final
+ * copy an odd launch count adds.  Host only.  Errors: E_ARG.
+ */
+int stencil_life_launches(int64_t ny, int64_t nx, int64_t T, int64_t *launches);
 
 /*
  * stencil_plan_info -- read back plan parameters (any pointer may be NULL):

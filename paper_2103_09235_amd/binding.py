@@ -32,7 +32,7 @@ STENCIL_E_STATE = -5
 EXPORTS = (
     "stencil_plan_create", "stencil_fold_weights", "stencil_fold_weights_f32",
     "stencil_plan_set_mode", "stencil_plan_set_fusion", "stencil_plan_separable",
-    "stencil_plan_set_floor", "stencil_life",
+    "stencil_plan_set_floor", "stencil_life", "stencil_life_launches",
     "stencil_plan_info",
     "stencil_profitability", "stencil_run", "stencil_run_schedule", "stencil_run_batched", "stencil_residual",
     "stencil_plan_destroy", "stencil_last_error", "stencil_version",
@@ -91,6 +91,7 @@ def _load() -> ctypes.CDLL:
     lib.stencil_plan_separable.argtypes = [P, ip, ip]
     lib.stencil_plan_set_floor.argtypes = [P, P, ctypes.c_int, ctypes.c_int64]
     lib.stencil_life.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, P]
+    lib.stencil_life_launches.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, i64p]
     lib.stencil_plan_info.argtypes = [P, ip, ip, ip, ip, ip]
     lib.stencil_profitability.argtypes = [P, ctypes.c_int, i64p, i64p]
     lib.stencil_run.argtypes = [P, ctypes.POINTER(stencil_grid), ctypes.c_int64]
@@ -192,6 +193,12 @@ def stencil_life(cells, scratch, T: int, stream=None) -> None:
     st = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
     _check(lib.stencil_life(cells.data_ptr(), scratch.data_ptr(), cells.shape[0], cells.shape[1],
                             int(T), st))
+
+
+def stencil_life_launches(ny: int, nx: int, T: int) -> int:
+    out = ctypes.c_int64()
+    _check(lib.stencil_life_launches(ny, nx, T, ctypes.byref(out)))
+    return out.value
 
 
 def stencil_plan_info(plan) -> dict:

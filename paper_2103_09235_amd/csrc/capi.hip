@@ -378,6 +378,36 @@ int stencil_plan_set_floor(stencil_plan p, const void *floor, int dtype, int64_t
   return STENCIL_OK;
 }
 
+namespace stencil {
+namespace {
+// The generations of each launch of a Game of Life run: the largest of 16,
+// 8, 4, 2 allowed, else 1.
+std::vector<int> life_schedule(int64_t ny, int64_t nx, const void *a, const void *b, int64_t T) {
+  std::vector<int> ks;
+  const int kmax = life_max_steps(ny, nx, a, b);
+  for (int64_t left = T; left > 0;) {
+    int k = 1;
+    for (int c = 16; c >= 2; c /= 2)
+      if (c <= kmax && c <= left && 2 * c + 1 <= ny) {
+        k = c;
+        break;
+      }
+    ks.push_back(k);
+    left -= k;
+  }
+  return ks;
+}
+}  // namespace
+}  // namespace stencil
+
+int stencil_life_launches(int64_t ny, int64_t nx, int64_t T, int64_t *launches) {
+  set_error("");
+  if (ny < 1 || nx < 1 || T < 0 || !launches) return fail(STENCIL_E_ARG, "bad arguments");
+  // caller buffers from hipMalloc are 4-byte aligned
+  *launches = (int64_t)life_schedule(ny, nx, (void *)16, (void *)32, T).size();
+  return STENCIL_OK;
+}
+
 int stencil_life(void *cells, void *scratch, int64_t ny, int64_t nx, int64_t T, void *stream) {
   set_error("");
   if (!cells || !scratch) return fail(STENCIL_E_ARG, "cells and scratch must be non-NULL");
@@ -392,8 +422,11 @@ int stencil_life(void *cells, void *scratch, int64_t ny, int64_t nx, int64_t T, 
   hipStream_t s = (hipStream_t)stream;
   const uint8_t *src = (const uint8_t *)cells;
   uint8_t *dst = (uint8_t *)scratch;
-  for (int64_t t = 0; t < T; ++t) {
-    hipError_t e = launch_life(src, dst, ny, nx, s);
+  // generations in fused launches of 16, 8, 4 or 2 where the grid allows,
+  // the rest one per launch
+  for (int k : life_schedule(ny, nx, cells, scratch, T)) {
+    hipError_t e = k > 1 ? launch_life_fused(src, dst, ny, nx, k, s)
+                         : launch_life(src, dst, ny, nx, s);
     if (e != hipSuccess) return hip_fail(e, "life generation");
     const uint8_t *o = src;
     src = dst;

@@ -139,6 +139,10 @@ hipError_t launch_mfma2d(const SweepLaunch &L);
 std::vector<uint16_t> mfma_b_table(const std::vector<float> &w, int R);
 // Game of Life generations on a periodic uint8 grid (life.hip).
 hipError_t launch_life(const uint8_t *in, uint8_t *out, int64_t ny, int64_t nx, hipStream_t s);
+// K generations per launch (K in {2, 4, 8, 16}, K <= life_max_steps).
+int life_max_steps(int64_t ny, int64_t nx, const void *in, const void *out);
+hipError_t launch_life_fused(const uint8_t *in, uint8_t *out, int64_t ny, int64_t nx, int K,
+                             hipStream_t s);
 // Largest number of fused steps the 1D kernel takes per launch.
 int sweep1d_max_steps(const SweepLaunch &L);
 // 2D FP32 temporal blocking: the most steps one launch fuses (1 = none), and

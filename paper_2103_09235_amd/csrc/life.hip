@@ -4,8 +4,9 @@
 // it has exactly 3 live neighbours, or 2 and is alive itself.  The rule is
 // not linear, so it is never folded.
 //
-// Rows whose length is a multiple of 4: a thread updates 4 cells held in one
-// 32-bit word.  For each of the three rows it loads that word and the two
+// One generation per launch (k_life4, k_life1), or several (k_life_tb,
+// below).  Rows whose length is a multiple of 4: a thread updates 4 cells
+// held in one 32-bit word.  For each of the three rows it loads that word and the two
 // bytes beside it; the 3-cell horizontal sums of the 4 cells are formed
 // bytewise in one word (each byte stays below 10, so no byte carries into
 // the next), and the 8-neighbour count is the three rows' sums minus the
@@ -13,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -75,7 +77,142 @@ __global__ void k_life1(const uint8_t *__restrict__ in, uint8_t *__restrict__ ou
   }
 }
 
+// ---------------------------------------------------------------- K per pass
+//
+// Several generations per pass over HBM (temporal blocking, as the fused 2D
+// sweep): a wavefront streams a 256-cell strip (one 32-bit word of 4 cells
+// per lane) down y through K stages; stage s keeps the last two rows of
+// generation s it has seen and, when the next row arrives, emits generation
+// s+1 of the middle row to stage s+1.  The strip loses one valid cell per
+// generation at each end and stores the middle 256 - 2B (B = K rounded up to
+// a word); a strip of BY rows streams BY + 2K rows.
+
+// Lane i receives lane i-1's (shr) or lane i+1's (shl) word; end lanes 0.
+__device__ __forceinline__ uint32_t word_from_left(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x138, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t word_from_right(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x130, 0xF, 0xF, true);
+}
+
+// Bytewise: 0x80 in each byte of x that is zero (bytes < 0x80).
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t x) {
+  return ~((((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x)) & 0x80808080u;
+}
+
+// The rule on 4 cells at once: count and self hold one byte per cell.
+__device__ __forceinline__ uint32_t rule4_swar(uint32_t self, uint32_t count) {
+  const uint32_t eq3 = zero_bytes(count ^ 0x03030303u);
+  const uint32_t eq2 = zero_bytes(count ^ 0x02020202u);
+  return (eq3 | (eq2 & (self << 7))) >> 7;
+}
+
+// 3-cell horizontal sums of the lane's 4 cells (neighbour bytes by DPP).
+__device__ __forceinline__ uint32_t hsum(uint32_t w) {
+  const uint32_t l = word_from_left(w), r = word_from_right(w);
+  return ((w << 8) | (l >> 24)) + w + ((w >> 8) | (r << 24));
+}
+
+template <int K>
+__global__ void __launch_bounds__(64)
+k_life_tb(const uint8_t *__restrict__ in, uint8_t *__restrict__ out, int ny, int nx, int BY,
+          int tiles_x) {
+  constexpr int B = (K + 3) / 4 * 4;
+  constexpr int WOUT = 256 - 2 * B;
+  const int lane = threadIdx.x;
+  const int t = blockIdx.x;
+  const int tx = t % tiles_x, ty = t / tiles_x;
+  const int xo0 = tx * WOUT, xi0 = xo0 - B;
+  const int y0 = ty * BY, y1 = min(y0 + BY, ny);
+  int gx = xi0 + 4 * lane;
+  gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+  const int lo = 4 * lane - B;
+  const bool store_ok = lo >= 0 && lo + 4 <= WOUT && xo0 + lo + 4 <= nx;
+  // per stage a ring of the last three rows of its generation (words and
+  // their horizontal sums), rotated by unrolling three rows
+  uint32_t rw[K][3], rh[K][3];
+#pragma unroll
+  for (int s = 0; s < K; ++s)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rw[s][i] = rh[s][i] = 0u;
+  const int jstart = y0 - K - 1, jend = y1 + K;  // level-0 rows streamed
+  auto row_word = [&](int j) {
+    j = j < 0 ? j + ny : (j >= ny ? j - ny : j);
+    return *reinterpret_cast<const uint32_t *>(in + (size_t)j * nx + gx);
+  };
+  uint32_t nxt = row_word(jstart);
+  for (int jb = jstart; jb < jend; jb += 3) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int j = jb + u;
+      // rows past jend re-read the last row and are never stored
+      uint32_t cur = nxt;
+      nxt = row_word(min(j + 1, jend - 1));
+      const int a = u % 3, b = (u + 1) % 3, c = (u + 2) % 3;  // prev, mid, incoming
+      // stage s: rows (prev, mid, cur) of generation s -> generation s+1 of mid
+#pragma unroll
+      for (int s = 0; s < K; ++s) {
+        const uint32_t hc = hsum(cur);
+        const uint32_t next = rule4_swar(rw[s][b], rh[s][a] + rh[s][b] + hc - rw[s][b]);
+        rw[s][c] = cur;
+        rh[s][c] = hc;
+        cur = next;  // generation s+1 of row j - 1 - s
+      }
+      const int yd = j - K;  // generation K of row yd is complete
+      if (store_ok && yd >= y0 && yd < y1)
+        *reinterpret_cast<uint32_t *>(out + (size_t)yd * nx + xo0 + lo) = cur;
+    }
+  }
+}
+
 }  // namespace
+
+// Generations one fused launch may take (the launches take 16, 8, 4 or 2);
+// 1 when the grid does not suit the fused kernel.
+int life_max_steps(int64_t ny, int64_t nx, const void *in, const void *out) {
+  if (nx % 4 != 0 || nx < 256 || ny < 33 || (uintptr_t)in % 4 != 0 || (uintptr_t)out % 4 != 0)
+    return 1;
+  if (nx > (1 << 30) || ny > (1 << 30)) return 1;
+  static const int cap = [] {
+    const char *e = std::getenv("STENCIL_LIFE_K");
+    return e ? std::max(1, std::min(16, std::atoi(e))) : 0;
+  }();
+  if (cap) return cap;
+  // While both grids fit the 256 MB last-level cache, HBM is not the limit
+  // and fewer fused generations (less redundant border work) run faster:
+  // 4 measured best at 5000^2 (16: -8%); larger grids fuse 16.
+  return ny * nx <= (int64_t)(1 << 27) ? 4 : 16;
+}
+
+template <int K>
+static hipError_t launch_tb(const uint8_t *in, uint8_t *out, int ny, int nx, hipStream_t s) {
+  constexpr int WOUT = 256 - 2 * ((K + 3) / 4 * 4);
+  const int tiles_x = (nx + WOUT - 1) / WOUT;
+  static const int env_by = [] {
+    const char *e = std::getenv("STENCIL_LIFE_ROWS");
+    return e ? std::atoi(e) : 0;
+  }();
+  const int target_y = std::max(1, 4096 / tiles_x);
+  int by = env_by > 0 ? std::max(env_by, 2 * K) : std::max((ny + target_y - 1) / target_y, 4 * K);
+  by = std::min(by, ny);
+  const int tiles_y = (ny + by - 1) / by;
+  const int64_t blocks = (int64_t)tiles_x * tiles_y;
+  if (blocks > (1LL << 31) - 1) return hipErrorNotSupported;
+  hipLaunchKernelGGL(k_life_tb<K>, dim3((unsigned)blocks), dim3(64), 0, s, in, out, ny, nx, by,
+                     tiles_x);
+  return hipGetLastError();
+}
+
+hipError_t launch_life_fused(const uint8_t *in, uint8_t *out, int64_t ny, int64_t nx, int K,
+                             hipStream_t s) {
+  switch (K) {
+    case 16: return launch_tb<16>(in, out, (int)ny, (int)nx, s);
+    case 8: return launch_tb<8>(in, out, (int)ny, (int)nx, s);
+    case 4: return launch_tb<4>(in, out, (int)ny, (int)nx, s);
+    case 2: return launch_tb<2>(in, out, (int)ny, (int)nx, s);
+    default: return hipErrorNotSupported;
+  }
+}
 
 hipError_t launch_life(const uint8_t *in, uint8_t *out, int64_t ny, int64_t nx, hipStream_t s) {
   const bool words = nx % 4 == 0 && (uintptr_t)in % 4 == 0 && (uintptr_t)out % 4 == 0;

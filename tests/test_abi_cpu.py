@@ -272,3 +272,12 @@ def test_floor_and_life_validation():
     assert L(1 << 20, 1 << 21, 8, 8, -1, None) == sf.STENCIL_E_ARG
     assert L(1 << 20, (1 << 20) + 8, 8, 8, 1, None) == sf.STENCIL_E_ARG  # overlap
     assert L(1 << 20, 1 << 21, 8, 8, 0, None) == sf.STENCIL_OK
+
+
+def test_life_launch_plan():
+    # 5000^2 fits the last-level cache: 4 generations per launch
+    assert sf.stencil_life_launches(5000, 5000, 1000) == 250
+    assert sf.stencil_life_launches(5000, 5000, 7) == 3      # 4 + 2 + 1
+    assert sf.stencil_life_launches(64, 96, 9) == 9          # too narrow: one per launch
+    assert sf.stencil_life_launches(20, 1024, 9) == 9        # fewer than 33 rows: one per launch
+    assert sf.stencil_life_launches(16384, 16384, 33) == 3   # 16 + 16 + 1

@@ -599,7 +599,10 @@ def test_apop_floor_bit_exact(n, T, f32, fusion):
 
 
 @pytest.mark.parametrize("shape,T", [((64, 96), 9), ((37, 41), 6), ((5000, 5000), 3),
-                                     ((3, 4), 5), ((1, 8), 2)])
+                                     ((3, 4), 5), ((1, 8), 2),
+                                     # fused generations (16, 8, 4, 2 per launch)
+                                     ((300, 1024), 37), ((33, 256), 16), ((100, 260), 30),
+                                     ((512, 5000), 19)])
 def test_life_bit_exact(shape, T):
     g = np.random.default_rng(shape[0] * 7 + shape[1]).integers(0, 2, size=shape).astype(np.uint8)
     cells = torch.from_numpy(g).to(DEV)
