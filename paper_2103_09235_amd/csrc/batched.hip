@@ -7,9 +7,11 @@
 // (one wavefront streams one tile, as in the single-grid 2D sweep), sorts
 // them by decreasing cost, and each workgroup takes tiles round-robin,
 // branching per tile (never per lane) to the kernel variant of that grid's
-// operator.  The ceil(T/m)-ish launches of the time loop, plus one copy for
-// grids whose sweep count is odd, are captured once in a hipGraph and
-// replayed.  The fold depth m of each grid is chosen per (stencil, size
+// operator.  Grids of at least 256 columns instead run their
+// (folded) applications several per launch in fused strips, before the
+// one-step launches of the rest.  All launches of the time loop, plus one
+// copy for grids whose launch count is odd, are captured once in a hipGraph
+// and replayed.  The fold depth m of each grid is chosen per (stencil, size
 // class) by timing the candidates on the device (the paper leaves parameter
 // tuning to future work, evaluation section) and cached on disk.
 #include <hip/hip_runtime.h>
@@ -45,6 +47,11 @@ struct GridInfo {
   int q, s;          // folded sweeps first, then plain sweeps
   int var_f, var_p;  // kernel variant of the folded and the plain operator
   int w_f, w_p;      // offsets of their weights in the weight table
+  // Grids of at least 256 columns fuse the folded (or, at
+  // m = 1, the plain) applications: fpass launches of the fused kernel
+  // first, apps applications spread evenly (the first apps % fpass take one
+  // more); the one-step launches then run the plain remainder only.
+  int fpass, apps;
 };
 
 struct Tile {
@@ -67,12 +74,15 @@ k_batched(const Tile *__restrict__ tiles, int ntiles, const GridInfo *__restrict
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const Tile tl = tiles[t];
     const GridInfo g = grids[tl.grid];
-    if (k >= g.q + g.s) continue;
-    const bool folded = k < g.q;
+    // fused grids: only the plain remainder (s sweeps) after fpass passes
+    const int q = g.fpass ? 0 : g.q;
+    if (k >= q + g.s) continue;
+    const bool folded = k < q;
     const int var = folded ? g.var_f : g.var_p;
     const WPtr<float> w{wtab + (folded ? g.w_f : g.w_p)};
-    const float *in = (k & 1) ? g.scratch : g.data;
-    float *out = (k & 1) ? g.data : g.scratch;
+    const int par = (k + g.fpass) & 1;
+    const float *in = par ? g.scratch : g.data;
+    float *out = par ? g.data : g.scratch;
     switch (var) {
       case variant_id(1, false, false):
         sweep2d_tile<float, 1, MASK_BOX, 4, 1, true, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, lds);
@@ -100,6 +110,168 @@ k_batched(const Tile *__restrict__ tiles, int ntiles, const GridInfo *__restrict
         break;
     }
   }
+}
+
+// ------------------------------------------------------------ fused passes
+//
+// The fused 2D strip (several applications of one operator per pass, one
+// wavefront per 256-column strip streaming down y, each application a
+// pipeline stage with its own accumulator queue, neighbour columns by DPP;
+// the single-grid form is described with the fused 2D sweep) with the number
+// of applications K <= KMAX chosen at run time: every stage is compiled, the
+// ones beyond K are skipped by a uniform branch.  Strips keep the KMAX
+// border, so one tiling serves every K.  Canonical order, bit-identical to
+// K single applications.
+
+constexpr int kTbRows = 128;
+
+__device__ __forceinline__ float tb_from_left(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
+                                                                0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float tb_from_right(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
+                                                                0x130, 0xF, 0xF, true));
+}
+
+__host__ __device__ constexpr int tb_border(int K, int R) { return (K * R + 3) / 4 * 4; }
+__host__ __device__ constexpr int tb_kmax(int R) { return R == 1 ? 8 : 4; }
+
+// VEC: rows of whole 16-byte vectors (one vector load and store per lane and
+// row); otherwise four scalar loads, each column wrapped on its own, and
+// stores column by column.
+template <int R, int MASK, bool VEC>
+__device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, int ny, int nx,
+                         int xo0, int y0, int y1, int K, const float *__restrict__ wt) {
+  using k2d::fmat;
+  using k2d::in_mask;
+  using k2d::load_vec;
+  using k2d::store_vec;
+  using k2d::wrap1;
+  constexpr int S = 2 * R + 1;
+  constexpr int NU = S;
+  constexpr int KMAX = tb_kmax(R);
+  constexpr int B = tb_border(KMAX, R);
+  constexpr int WOUT = 256 - 2 * B;
+  float W[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) W[i] = wt[i];
+  const int lane = threadIdx.x;
+  const int gx = wrap1(xo0 - B + 4 * lane, nx);
+  int gxs[4];  // scalar path: each column wrapped on its own
+#pragma unroll
+  for (int v = 0; v < 4; ++v) gxs[v] = wrap1(xo0 - B + 4 * lane + v, nx);
+  const int lo = 4 * lane - B;
+  const bool store_ok = lo >= 0 && lo + 4 <= WOUT && xo0 + lo + 4 <= nx;
+  bool store_v[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) store_v[v] = lo + v >= 0 && lo + v < WOUT && xo0 + lo + v < nx;
+  const int jstart = y0 - K * R, jend = y1 + K * R;
+  float acc[KMAX][NU][4];
+#pragma unroll
+  for (int st = 0; st < KMAX; ++st)
+#pragma unroll
+    for (int k = 0; k < NU; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[st][k][v] = 0.0f;
+  auto row = [&](const int j, const int u, const float (&in_row)[4]) {
+    float cur[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) cur[v] = in_row[v];
+#pragma unroll
+    for (int st = 0; st < KMAX; ++st) {
+      if (st < K) {
+        float win[4 + 2 * R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) win[i] = tb_from_left(cur[4 - R + i]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) win[R + v] = cur[v];
+#pragma unroll
+        for (int i = 0; i < R; ++i) win[R + 4 + i] = tb_from_right(cur[i]);
+#pragma unroll
+        for (int k = S - 1; k >= 0; --k) {
+          const int slot = (u + k) % NU;
+          const int oy = R - k;
+#pragma unroll
+          for (int ox = -R; ox <= R; ++ox) {
+            if (in_mask<MASK, R>(oy, ox)) {
+              const float w = W[(oy + R) * S + (ox + R)];
+              const bool first = k == S - 1 && ox == (MASK == MASK_BOX ? -R : 0);
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                acc[st][slot][v] = fmat(w, win[R + v + ox], first ? 0.0f : acc[st][slot][v]);
+            }
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cur[v] = acc[st][u % NU][v];
+      }
+    }
+    const int yd = j - K * R;
+    if (yd >= y0 && yd < y1) {
+      float *dst = out + (size_t)yd * nx + xo0 + lo;
+      if constexpr (VEC) {
+        if (store_ok) store_vec<float, 4>(dst, cur);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (store_v[v]) dst[v] = cur[v];
+      }
+    }
+  };
+  auto fetch = [&](const int j0, float (&buf)[NU][4]) {
+#pragma unroll
+    for (int p = 0; p < NU; ++p) {
+      const float *rowp = in + (size_t)wrap1(min(j0 + p, jend - 1), ny) * nx;
+      if constexpr (VEC) {
+        load_vec<float, 4>(rowp + gx, buf[p]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) buf[p][v] = rowp[gxs[v]];
+      }
+    }
+  };
+  float bufA[NU][4], bufB[NU][4];
+  fetch(jstart, bufA);
+  for (int jb = jstart; jb < jend; jb += 2 * NU) {
+    fetch(jb + NU, bufB);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) row(jb + u, u, bufA[u]);
+    fetch(jb + 2 * NU, bufA);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) row(jb + NU + u, u, bufB[u]);
+  }
+}
+
+// One fused pass of every fused grid that has pass k: one block per strip.
+__global__ void __launch_bounds__(64)
+k_batched_tb(const Tile *__restrict__ tiles, int ntiles, const GridInfo *__restrict__ grids,
+             const float *__restrict__ wtab, int k) {
+  const Tile tl = tiles[blockIdx.x];
+  const GridInfo g = grids[tl.grid];
+  if (k >= g.fpass) return;
+  const int b = g.apps / g.fpass, e = g.apps % g.fpass;
+  const int K = b + (k < e ? 1 : 0);
+  const float *in = (k & 1) ? g.scratch : g.data;
+  float *out = (k & 1) ? g.data : g.scratch;
+  const float *w = wtab + g.w_f;
+#define TB_VARIANT(R, DIAMOND, VEC)                                                       \
+  case variant_id(R, DIAMOND, VEC):                                                        \
+    tb_strip<R, DIAMOND ? MASK_DIAMOND : MASK_BOX, VEC>(in, out, g.ny, g.nx, tl.x0, tl.y0, \
+                                                        tl.y1, K, w);                      \
+    break;
+  switch (g.var_f) {
+    TB_VARIANT(1, false, true)
+    TB_VARIANT(1, true, true)
+    TB_VARIANT(2, false, true)
+    TB_VARIANT(2, true, true)
+    TB_VARIANT(1, false, false)
+    TB_VARIANT(1, true, false)
+    TB_VARIANT(2, false, false)
+    TB_VARIANT(2, true, false)
+    default: break;
+  }
+#undef TB_VARIANT
 }
 
 // Grids whose total sweep count is odd end in scratch: copy them back.
@@ -187,9 +359,11 @@ int tune_one(stencil_plan p, int side, int max_m, hipStream_t stream, int *best_
     stencil_plan_s tmp = *p;  // same weights, own fold depth and device state
     tmp.dev.clear();
     tmp.batch_w32.clear();
-    // the batched kernel applies the operator once per launch: time that
+    // time what the batch runs: VECTOR kernels, fused passes where the grid
+    // allows them (the batched passes fuse as the single-grid sweep does for
+    // radius <= 2)
     tmp.mode = STENCIL_MODE_VECTOR;
-    tmp.max_fuse = 1;
+    tmp.max_fuse = 0;
     rc = stencil_fold_weights(&tmp, m, nullptr, nullptr);
     if (rc) break;
     stencil_grid g{};
@@ -230,6 +404,8 @@ int tune_one(stencil_plan p, int side, int max_m, hipStream_t stream, int *best_
 struct BatchEntry {
   std::string key;
   int device = 0;
+  Tile *d_tiles_tb = nullptr;  // fused strips (one block each)
+  int ntiles_tb = 0, launches_tb = 0;
   Tile *d_tiles = nullptr;
   GridInfo *d_grids = nullptr;
   float *d_w = nullptr;
@@ -251,6 +427,7 @@ void free_entry(BatchEntry &b) {
   if (b.exec) (void)hipGraphExecDestroy(b.exec);
   if (b.graph) (void)hipGraphDestroy(b.graph);
   if (b.d_tiles) (void)hipFree(b.d_tiles);
+  if (b.d_tiles_tb) (void)hipFree(b.d_tiles_tb);
   if (b.d_grids) (void)hipFree(b.d_grids);
   if (b.d_w) (void)hipFree(b.d_w);
   if (b.d_odd) (void)hipFree(b.d_odd);
@@ -258,6 +435,12 @@ void free_entry(BatchEntry &b) {
 }
 
 hipError_t enqueue(const BatchEntry &b, hipStream_t s) {
+  for (int k = 0; k < b.launches_tb; ++k) {
+    hipLaunchKernelGGL(k_batched_tb, dim3(b.ntiles_tb), dim3(64), 0, s, b.d_tiles_tb,
+                       b.ntiles_tb, b.d_grids, b.d_w, k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   for (int k = 0; k < b.launches; ++k) {
     hipLaunchKernelGGL(k_batched, dim3(b.nblocks), dim3(64), 0, s, b.d_tiles, b.ntiles,
                        b.d_grids, b.d_w, k);
@@ -328,7 +511,11 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
     if (it != tab.end()) {
       m = it->second;
     } else if (autotune) {
-      const int rep_side = (int)std::min<int64_t>(side, 1 << 12);
+      // a representative of the class that runs as the batch will: sides of
+      // 256 and more fuse their passes in the batch, so time a vector-aligned
+      // side (which the single-grid sweep fuses too)
+      int rep_side = (int)std::min<int64_t>(side, 1 << 12);
+      if (rep_side >= 256) rep_side = (rep_side + 3) / 4 * 4;
       int rc = tune_one(p, rep_side, max_m, stream, &m);
       if (rc) return rc;
       tab[key] = m;
@@ -373,9 +560,9 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
       woff[{p, m}] = *off;
       return STENCIL_OK;
     };
-    std::vector<std::pair<int64_t, Tile>> tiles;
+    std::vector<std::pair<int64_t, Tile>> tiles, tiles_tb;
     std::vector<int> odd;
-    int launches = 0;
+    int launches = 0, launches_tb = 0;
     for (int i = 0; i < count; ++i) {
       const stencil_plan p = plans[i];
       const stencil_grid &g = grids[i];
@@ -396,33 +583,73 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
       if (rc) return rc;
       G.w_f = G.w_p;
       if (m > 1 && (rc = weights_at(p, m, &G.w_f))) return rc;
-      const int sweeps = G.q + G.s;
-      launches = std::max(launches, sweeps);
-      if (sweeps % 2) odd.push_back(i);
-      const int bx = 256;
       const int R = m * p->r;
-      for (int y0 = 0; y0 < G.ny; y0 += kTileRows)
-        for (int x0 = 0; x0 < G.nx; x0 += bx) {
-          const int y1 = std::min(G.ny, y0 + kTileRows);
-          const int64_t cost = (int64_t)(y1 - y0 + 2 * R) * (2 * R + 1);
-          tiles.push_back({cost, Tile{i, x0, y0, y1}});
+      // fused passes: the folded applications (the plain ones at m = 1) of
+      // grids of >= 256 vector-aligned columns, up to tb_kmax(R) per pass
+      G.fpass = 0;
+      G.apps = 0;
+      if (G.nx >= 256 && R <= kMaxBatchRadius && G.ny >= 2 * tb_kmax(R) * R + 1) {
+        G.apps = m > 1 ? G.q : G.s;
+        const int rest = m > 1 ? G.s : 0;
+        if (G.apps > 1) {
+          G.fpass = (G.apps + tb_kmax(R) - 1) / tb_kmax(R);
+          if ((G.fpass + rest) % 2 && G.fpass < G.apps) ++G.fpass;  // even: no copy back
+          G.q = 0;
+          G.s = rest;
+        } else {
+          G.apps = 0;
         }
+      }
+      const int sweeps = G.fpass + (G.fpass ? G.s : G.q + G.s);
+      launches = std::max(launches, G.fpass ? G.s : G.q + G.s);
+      launches_tb = std::max(launches_tb, G.fpass);
+      if (sweeps % 2) odd.push_back(i);
+      if (G.fpass) {
+        constexpr int kWout1 = 256 - 2 * tb_border(tb_kmax(1), 1);
+        constexpr int kWout2 = 256 - 2 * tb_border(tb_kmax(2), 2);
+        const int wout = R == 1 ? kWout1 : kWout2;
+        const int kk = (G.apps + G.fpass - 1) / G.fpass;
+        for (int y0 = 0; y0 < G.ny; y0 += kTbRows)
+          for (int x0 = 0; x0 < G.nx; x0 += wout) {
+            const int y1 = std::min(G.ny, y0 + kTbRows);
+            const int64_t cost = (int64_t)(y1 - y0 + 2 * kk * R) * kk * (2 * R + 1);
+            tiles_tb.push_back({cost, Tile{i, x0, y0, y1}});
+          }
+      }
+      const int bx = 256;
+      const int Rp = G.fpass ? p->r : R;  // one-step work of fused grids is plain
+      if (G.fpass == 0 || G.s > 0)
+        for (int y0 = 0; y0 < G.ny; y0 += kTileRows)
+          for (int x0 = 0; x0 < G.nx; x0 += bx) {
+            const int y1 = std::min(G.ny, y0 + kTileRows);
+            const int64_t cost = (int64_t)(y1 - y0 + 2 * Rp) * (2 * Rp + 1);
+            tiles.push_back({cost, Tile{i, x0, y0, y1}});
+          }
     }
-    std::stable_sort(tiles.begin(), tiles.end(),
-                     [](const auto &a, const auto &b) { return a.first > b.first; });
-    std::vector<Tile> tl(tiles.size());
+    auto by_cost = [](const auto &a, const auto &b) { return a.first > b.first; };
+    std::stable_sort(tiles.begin(), tiles.end(), by_cost);
+    std::stable_sort(tiles_tb.begin(), tiles_tb.end(), by_cost);
+    std::vector<Tile> tl(tiles.size()), tltb(tiles_tb.size());
     for (size_t t = 0; t < tiles.size(); ++t) tl[t] = tiles[t].second;
+    for (size_t t = 0; t < tiles_tb.size(); ++t) tltb[t] = tiles_tb[t].second;
     b.ntiles = (int)tl.size();
+    b.ntiles_tb = (int)tltb.size();
     b.nodd = (int)odd.size();
-    b.launches = launches;
+    b.launches = b.ntiles ? launches : 0;
+    b.launches_tb = b.ntiles_tb ? launches_tb : 0;
+    if ((int64_t)b.ntiles_tb > (1LL << 31) - 1) return fail(STENCIL_E_UNSUPPORTED, "batch too large");
     hipDeviceProp_t prop;
     STENCIL_HIP_TRY(hipGetDeviceProperties(&prop, device));
     b.nblocks = std::max(1, std::min(b.ntiles, prop.multiProcessorCount * 32));
-    hipError_t e = hipMalloc(&b.d_tiles, sizeof(Tile) * tl.size());
+    hipError_t e = hipMalloc(&b.d_tiles, sizeof(Tile) * std::max<size_t>(1, tl.size()));
+    if (e == hipSuccess) e = hipMalloc(&b.d_tiles_tb, sizeof(Tile) * std::max<size_t>(1, tltb.size()));
+    if (e == hipSuccess && !tltb.empty())
+      e = hipMemcpy(b.d_tiles_tb, tltb.data(), sizeof(Tile) * tltb.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&b.d_grids, sizeof(GridInfo) * gi.size());
     if (e == hipSuccess) e = hipMalloc(&b.d_w, sizeof(float) * std::max<size_t>(1, wt.size()));
     if (e == hipSuccess) e = hipMalloc(&b.d_odd, sizeof(int) * std::max<size_t>(1, odd.size()));
-    if (e == hipSuccess) e = hipMemcpy(b.d_tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tl.empty())
+      e = hipMemcpy(b.d_tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b.d_grids, gi.data(), sizeof(GridInfo) * gi.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !wt.empty()) e = hipMemcpy(b.d_w, wt.data(), sizeof(float) * wt.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !odd.empty()) e = hipMemcpy(b.d_odd, odd.data(), sizeof(int) * odd.size(), hipMemcpyHostToDevice);

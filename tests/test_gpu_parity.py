@@ -619,3 +619,21 @@ def test_life_glider_on_gpu():
     sf.stencil_life(cells, torch.empty_like(cells), 64)
     torch.cuda.synchronize()
     assert np.array_equal(cells.cpu().numpy(), np.roll(g, (16, 16), axis=(0, 1)))
+
+
+@pytest.mark.parametrize("T,m", [(50, 1), (21, 2), (3, 1)])
+def test_batched_fused_passes_bit_exact(tmp_path, T, m):
+    """Grids of >= 256 vector-aligned columns run fused passes (K split
+    evenly, e.g. 50 = 8 + 7 x 6), the rest one step per launch, then the
+    plain remainder: every grid bit-exact against the oracle's mirror."""
+    sides = [512, 1024, 260, 300, 64, 256]
+    kinds = [synth.STAR, synth.BOX, synth.STAR, synth.BOX, synth.STAR, synth.BOX]
+    weights = [synth.WORKLOADS["star2d"].weights, synth.WORKLOADS["box2d"].weights] * 3
+    grids = [synth.grid_f32((s, s), stream=5 + i) for i, s in enumerate(sides)]
+    cache = tmp_path / "m.txt"
+    cache.write_text("".join("stencil-batched-m %d 1 %d %d\n" % (sh, c, m)
+                             for sh in (0, 1) for c in range(5, 12)))
+    outs, chosen = _run_batched(kinds, weights, grids, T, tune_cache=str(cache), max_m=m)
+    assert chosen == [m] * len(grids)
+    for g, w, o in zip(grids, weights, outs):
+        assert np.array_equal(o, oracle.folded_reference_f32(w, g, T, m))
