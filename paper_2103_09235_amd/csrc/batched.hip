@@ -49,9 +49,9 @@ struct GridInfo {
   int w_f, w_p;      // offsets of their weights in the weight table
   // Grids of at least 256 columns fuse the folded (or, at
   // m = 1, the plain) applications: fpass launches of the fused kernel
-  // first, apps applications spread evenly (the first apps % fpass take one
-  // more); the one-step launches then run the plain remainder only.
-  int fpass, apps;
+  // first, nfull of KMAX applications and then one of the remaining tail
+  // (< KMAX); the one-step launches then run the plain remainder only.
+  int fpass, nfull, tail;
 };
 
 struct Tile {
@@ -118,12 +118,21 @@ k_batched(const Tile *__restrict__ tiles, int ntiles, const GridInfo *__restrict
 // wavefront per 256-column strip streaming down y, each application a
 // pipeline stage with its own accumulator queue, neighbour columns by DPP;
 // the single-grid form is described with the fused 2D sweep) with the number
-// of applications K <= KMAX chosen at run time: every stage is compiled, the
-// ones beyond K are skipped by a uniform branch.  Strips keep the KMAX
-// border, so one tiling serves every K.  Canonical order, bit-identical to
-// K single applications.
+// of applications K <= KMAX.  Full passes compile K = KMAX.  A grid's
+// last, shorter pass runs all KMAX stages as well and stores stage K-1's
+// output, picked by a select: a branch per stage would make the compiler
+// drain every outstanding load where the branches merge, and a body per K
+// makes the kernel about twice as large, which measured 10% slower on a
+// mixed batch.  Strips keep the KMAX border, so one tiling serves every K.  Canonical order, bit-identical to K single
+// applications.
 
-constexpr int kTbRows = 128;
+static int tb_rows() {
+  static const int rows = [] {
+    const char *e = std::getenv("STENCIL_BATCH_TB_ROWS");
+    return e ? std::max(16, std::atoi(e)) : 64;
+  }();
+  return rows;
+}
 
 __device__ __forceinline__ float tb_from_left(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
@@ -140,9 +149,9 @@ __host__ __device__ constexpr int tb_kmax(int R) { return R == 1 ? 8 : 4; }
 // VEC: rows of whole 16-byte vectors (one vector load and store per lane and
 // row); otherwise four scalar loads, each column wrapped on its own, and
 // stores column by column.
-template <int R, int MASK, bool VEC>
+template <int R, int MASK, bool VEC, bool FULL>
 __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, int ny, int nx,
-                         int xo0, int y0, int y1, int K, const float *__restrict__ wt) {
+                         int xo0, int y0, int y1, int Kr, const float *__restrict__ wt) {
   using k2d::fmat;
   using k2d::in_mask;
   using k2d::load_vec;
@@ -153,6 +162,7 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
   constexpr int KMAX = tb_kmax(R);
   constexpr int B = tb_border(KMAX, R);
   constexpr int WOUT = 256 - 2 * B;
+  const int K = FULL ? KMAX : Kr;
   float W[S * S];
 #pragma unroll
   for (int i = 0; i < S * S; ++i) W[i] = wt[i];
@@ -175,12 +185,12 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[st][k][v] = 0.0f;
   auto row = [&](const int j, const int u, const float (&in_row)[4]) {
-    float cur[4];
+    float cur[4], res[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) cur[v] = in_row[v];
+    for (int v = 0; v < 4; ++v) cur[v] = res[v] = in_row[v];
 #pragma unroll
     for (int st = 0; st < KMAX; ++st) {
-      if (st < K) {
+      {
         float win[4 + 2 * R];
 #pragma unroll
         for (int i = 0; i < R; ++i) win[i] = tb_from_left(cur[4 - R + i]);
@@ -205,17 +215,22 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) cur[v] = acc[st][u % NU][v];
+        if constexpr (!FULL) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) res[v] = st == K - 1 ? cur[v] : res[v];
+        }
       }
     }
     const int yd = j - K * R;
     if (yd >= y0 && yd < y1) {
       float *dst = out + (size_t)yd * nx + xo0 + lo;
+      const float(&val)[4] = FULL ? cur : res;
       if constexpr (VEC) {
-        if (store_ok) store_vec<float, 4>(dst, cur);
+        if (store_ok) store_vec<float, 4>(dst, val);
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          if (store_v[v]) dst[v] = cur[v];
+          if (store_v[v]) dst[v] = val[v];
       }
     }
   };
@@ -244,35 +259,38 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
 }
 
 // One fused pass of every fused grid that has pass k: one block per strip.
+// One kernel per radius and row layout, so that each gets its own register
+// allocation (a kernel holding every variant would run all of them at the
+// occupancy of the largest).
+template <int R, bool VEC>
 __global__ void __launch_bounds__(64)
-k_batched_tb(const Tile *__restrict__ tiles, int ntiles, const GridInfo *__restrict__ grids,
+k_batched_tb(const Tile *__restrict__ tiles, const GridInfo *__restrict__ grids,
              const float *__restrict__ wtab, int k) {
-  const Tile tl = tiles[blockIdx.x];
+  // each XCD (blocks are dealt to the 8 XCDs round-robin) takes one
+  // contiguous range of strips, so neighbouring strips share their
+  // overlapping rows and columns in one L2
+  const int bi = blockIdx.x, nb = gridDim.x;
+  const int x = bi & 7, q = nb >> 3, r = nb & 7;
+  const Tile tl = tiles[x * q + min(x, r) + (bi >> 3)];
   const GridInfo g = grids[tl.grid];
   if (k >= g.fpass) return;
-  const int b = g.apps / g.fpass, e = g.apps % g.fpass;
-  const int K = b + (k < e ? 1 : 0);
+  constexpr int KMAX = tb_kmax(R);
+  const int K = k < g.nfull ? KMAX : g.tail;
   const float *in = (k & 1) ? g.scratch : g.data;
   float *out = (k & 1) ? g.data : g.scratch;
   const float *w = wtab + g.w_f;
-#define TB_VARIANT(R, DIAMOND, VEC)                                                       \
-  case variant_id(R, DIAMOND, VEC):                                                        \
-    tb_strip<R, DIAMOND ? MASK_DIAMOND : MASK_BOX, VEC>(in, out, g.ny, g.nx, tl.x0, tl.y0, \
-                                                        tl.y1, K, w);                      \
-    break;
-  switch (g.var_f) {
-    TB_VARIANT(1, false, true)
-    TB_VARIANT(1, true, true)
-    TB_VARIANT(2, false, true)
-    TB_VARIANT(2, true, true)
-    TB_VARIANT(1, false, false)
-    TB_VARIANT(1, true, false)
-    TB_VARIANT(2, false, false)
-    TB_VARIANT(2, true, false)
-    default: break;
+  const bool dia = g.var_f == variant_id(R, true, VEC);
+  if (K == KMAX) {
+    if (dia) tb_strip<R, MASK_DIAMOND, VEC, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
+    else tb_strip<R, MASK_BOX, VEC, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
+  } else {
+    if (dia) tb_strip<R, MASK_DIAMOND, VEC, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
+    else tb_strip<R, MASK_BOX, VEC, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
   }
-#undef TB_VARIANT
 }
+
+// tile groups of the fused passes: (R - 1) * 2 + VEC
+constexpr int kTbGroups = 4;
 
 // Grids whose total sweep count is odd end in scratch: copy them back.
 __global__ void __launch_bounds__(256)
@@ -404,8 +422,9 @@ int tune_one(stencil_plan p, int side, int max_m, hipStream_t stream, int *best_
 struct BatchEntry {
   std::string key;
   int device = 0;
-  Tile *d_tiles_tb = nullptr;  // fused strips (one block each)
-  int ntiles_tb = 0, launches_tb = 0;
+  Tile *d_tiles_tb = nullptr;  // fused strips (one block each), by group
+  int tb_off[kTbGroups + 1] = {0, 0, 0, 0, 0};
+  int launches_tb = 0;
   Tile *d_tiles = nullptr;
   GridInfo *d_grids = nullptr;
   float *d_w = nullptr;
@@ -436,10 +455,19 @@ void free_entry(BatchEntry &b) {
 
 hipError_t enqueue(const BatchEntry &b, hipStream_t s) {
   for (int k = 0; k < b.launches_tb; ++k) {
-    hipLaunchKernelGGL(k_batched_tb, dim3(b.ntiles_tb), dim3(64), 0, s, b.d_tiles_tb,
-                       b.ntiles_tb, b.d_grids, b.d_w, k);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    for (int grp = 0; grp < kTbGroups; ++grp) {
+      const int n = b.tb_off[grp + 1] - b.tb_off[grp];
+      if (n == 0) continue;
+      const Tile *t = b.d_tiles_tb + b.tb_off[grp];
+      switch (grp) {
+        case 0: hipLaunchKernelGGL((k_batched_tb<1, false>), dim3(n), dim3(64), 0, s, t, b.d_grids, b.d_w, k); break;
+        case 1: hipLaunchKernelGGL((k_batched_tb<1, true>), dim3(n), dim3(64), 0, s, t, b.d_grids, b.d_w, k); break;
+        case 2: hipLaunchKernelGGL((k_batched_tb<2, false>), dim3(n), dim3(64), 0, s, t, b.d_grids, b.d_w, k); break;
+        default: hipLaunchKernelGGL((k_batched_tb<2, true>), dim3(n), dim3(64), 0, s, t, b.d_grids, b.d_w, k); break;
+      }
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   for (int k = 0; k < b.launches; ++k) {
     hipLaunchKernelGGL(k_batched, dim3(b.nblocks), dim3(64), 0, s, b.d_tiles, b.ntiles,
@@ -448,7 +476,9 @@ hipError_t enqueue(const BatchEntry &b, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   if (b.nodd > 0) {
-    hipLaunchKernelGGL(k_batched_copyback, dim3(64, std::min(b.nodd, 4096)), dim3(256), 0, s,
+    // enough blocks per grid that a few large grids still fill the chip
+    const int by = std::min(b.nodd, 4096), bx = std::max(64, 4096 / by);
+    hipLaunchKernelGGL(k_batched_copyback, dim3(bx, by), dim3(256), 0, s,
                        b.d_grids, b.d_odd, b.nodd);
     return hipGetLastError();
   }
@@ -560,7 +590,7 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
       woff[{p, m}] = *off;
       return STENCIL_OK;
     };
-    std::vector<std::pair<int64_t, Tile>> tiles, tiles_tb;
+    std::vector<std::pair<int64_t, Tile>> tiles, tiles_tb[kTbGroups];
     std::vector<int> odd;
     int launches = 0, launches_tb = 0;
     for (int i = 0; i < count; ++i) {
@@ -586,18 +616,21 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
       const int R = m * p->r;
       // fused passes: the folded applications (the plain ones at m = 1) of
       // grids of >= 256 vector-aligned columns, up to tb_kmax(R) per pass
-      G.fpass = 0;
-      G.apps = 0;
+      G.fpass = G.nfull = G.tail = 0;
       if (G.nx >= 256 && R <= kMaxBatchRadius && G.ny >= 2 * tb_kmax(R) * R + 1) {
-        G.apps = m > 1 ? G.q : G.s;
+        const int apps = m > 1 ? G.q : G.s;
         const int rest = m > 1 ? G.s : 0;
-        if (G.apps > 1) {
-          G.fpass = (G.apps + tb_kmax(R) - 1) / tb_kmax(R);
-          if ((G.fpass + rest) % 2 && G.fpass < G.apps) ++G.fpass;  // even: no copy back
+        const int KM = tb_kmax(R);
+        if (apps > 1) {
+          // full passes, then the remainder.  An odd launch count is not
+          // made even by splitting a pass: a pass costs about the same time
+          // whatever its K (it is bound by the strips' memory latency),
+          // more than copying the grid back
+          G.nfull = apps / KM;
+          G.tail = apps % KM;
+          G.fpass = G.nfull + (G.tail > 0);
           G.q = 0;
           G.s = rest;
-        } else {
-          G.apps = 0;
         }
       }
       const int sweeps = G.fpass + (G.fpass ? G.s : G.q + G.s);
@@ -608,12 +641,13 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
         constexpr int kWout1 = 256 - 2 * tb_border(tb_kmax(1), 1);
         constexpr int kWout2 = 256 - 2 * tb_border(tb_kmax(2), 2);
         const int wout = R == 1 ? kWout1 : kWout2;
-        const int kk = (G.apps + G.fpass - 1) / G.fpass;
-        for (int y0 = 0; y0 < G.ny; y0 += kTbRows)
+        const int kk = G.nfull ? tb_kmax(R) : G.tail;
+        const int rows = tb_rows();
+        for (int y0 = 0; y0 < G.ny; y0 += rows)
           for (int x0 = 0; x0 < G.nx; x0 += wout) {
-            const int y1 = std::min(G.ny, y0 + kTbRows);
+            const int y1 = std::min(G.ny, y0 + rows);
             const int64_t cost = (int64_t)(y1 - y0 + 2 * kk * R) * kk * (2 * R + 1);
-            tiles_tb.push_back({cost, Tile{i, x0, y0, y1}});
+            tiles_tb[(R - 1) * 2 + (vx4 ? 1 : 0)].push_back({cost, Tile{i, x0, y0, y1}});
           }
       }
       const int bx = 256;
@@ -628,16 +662,22 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
     }
     auto by_cost = [](const auto &a, const auto &b) { return a.first > b.first; };
     std::stable_sort(tiles.begin(), tiles.end(), by_cost);
-    std::stable_sort(tiles_tb.begin(), tiles_tb.end(), by_cost);
-    std::vector<Tile> tl(tiles.size()), tltb(tiles_tb.size());
+    std::vector<Tile> tl(tiles.size()), tltb;
     for (size_t t = 0; t < tiles.size(); ++t) tl[t] = tiles[t].second;
-    for (size_t t = 0; t < tiles_tb.size(); ++t) tltb[t] = tiles_tb[t].second;
+    for (int grp = 0; grp < kTbGroups; ++grp) {
+      // strips in grid, row band, column order (neighbours adjacent); every
+      // block is resident at once or nearly, so cost order matters little
+      static const bool by_cost_env = std::getenv("STENCIL_BATCH_TB_SORT") != nullptr;
+      if (by_cost_env) std::stable_sort(tiles_tb[grp].begin(), tiles_tb[grp].end(), by_cost);
+      b.tb_off[grp] = (int)tltb.size();
+      for (const auto &ct : tiles_tb[grp]) tltb.push_back(ct.second);
+    }
+    b.tb_off[kTbGroups] = (int)tltb.size();
+    if (tltb.size() > (size_t)((1LL << 31) - 1)) return fail(STENCIL_E_UNSUPPORTED, "batch too large");
     b.ntiles = (int)tl.size();
-    b.ntiles_tb = (int)tltb.size();
     b.nodd = (int)odd.size();
     b.launches = b.ntiles ? launches : 0;
-    b.launches_tb = b.ntiles_tb ? launches_tb : 0;
-    if ((int64_t)b.ntiles_tb > (1LL << 31) - 1) return fail(STENCIL_E_UNSUPPORTED, "batch too large");
+    b.launches_tb = tltb.empty() ? 0 : launches_tb;
     hipDeviceProp_t prop;
     STENCIL_HIP_TRY(hipGetDeviceProperties(&prop, device));
     b.nblocks = std::max(1, std::min(b.ntiles, prop.multiProcessorCount * 32));

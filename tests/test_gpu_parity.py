@@ -621,11 +621,13 @@ def test_life_glider_on_gpu():
     assert np.array_equal(cells.cpu().numpy(), np.roll(g, (16, 16), axis=(0, 1)))
 
 
-@pytest.mark.parametrize("T,m", [(50, 1), (21, 2), (3, 1)])
+@pytest.mark.parametrize("T,m", [(50, 1), (21, 2), (3, 1), (13, 1), (15, 2), (2, 1), (16, 1)])
 def test_batched_fused_passes_bit_exact(tmp_path, T, m):
-    """Grids of >= 256 vector-aligned columns run fused passes (K split
-    evenly, e.g. 50 = 8 + 7 x 6), the rest one step per launch, then the
-    plain remainder: every grid bit-exact against the oracle's mirror."""
+    """Grids of >= 256 columns run fused passes (full passes of 8 plain
+    applications at radius 1, 4 at radius 2, then one pass of the remainder,
+    e.g. 50 = 6 x 8 + 2), the narrower ones one step per launch, then the
+    plain remainder; odd launch counts end in a copy back.  Every grid
+    bit-exact against the oracle's mirror."""
     sides = [512, 1024, 260, 300, 64, 256]
     kinds = [synth.STAR, synth.BOX, synth.STAR, synth.BOX, synth.STAR, synth.BOX]
     weights = [synth.WORKLOADS["star2d"].weights, synth.WORKLOADS["box2d"].weights] * 3
