@@ -68,10 +68,13 @@ def parse():
                     help="time only this fold depth (profiling runs)")
     ap.add_argument("--only-mode", default="",
                     choices=["", "vector", "vector_unfused", "symmetric", "separable",
-                             "mfma_bf16x3"],
+                             "mfma_bf16x3", "vector_graph", "tuned"],
                     help="time only this kernel family (profiling runs)")
     ap.add_argument("--no-per-grid", action="store_true",
                     help="batched: skip the per-grid-launch baseline (profiling runs)")
+    ap.add_argument("--tune-cache", default="",
+                    help="batched: fold-depth tuning cache file to use (and fill); "
+                         "default a fresh temporary file")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy (PMC byte-counter calibration)")
     return ap.parse_args()
@@ -105,7 +108,7 @@ def kernel_source_hash(family: str) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_key: str, workload: str):
+def traffic_from_profiles(kernel_key: str, workload: str, field: str = "hbm-bytes-per-launch"):
     """HBM bytes per launch from a committed rocprofv3 PMC summary, if one
     exists for this kernel and workload and the kernel's sources have not
     changed since it was taken (its 'source-hash' line)."""
@@ -116,7 +119,7 @@ def traffic_from_profiles(kernel_key: str, workload: str):
     m = re.search(r"source-hash:\s*(\w+)", text)
     if not m or m.group(1) != kernel_source_hash(kernel_family(kernel_key)):
         return None
-    b = re.search(r"hbm-bytes-per-launch:\s*([0-9.eE+]+)", text)
+    b = re.search(re.escape(field) + r":\s*([0-9.eE+]+)", text)
     return float(b.group(1)) if b else None
 
 
@@ -223,6 +226,9 @@ def bench_grid(args, wl_name):
         form_modes = []
         if m not in extra:
             form_modes.append(("vector", sf.STENCIL_MODE_VECTOR, 0))
+            if not zero_bc:
+                # the same launches captured once in a hipGraph and replayed
+                form_modes.append(("vector_graph", sf.STENCIL_MODE_VECTOR, 0))
             if wl.dim == 2 and f32 and not zero_bc:
                 form_modes.append(("vector_unfused", sf.STENCIL_MODE_VECTOR, 1))
         if symmetric:
@@ -247,6 +253,7 @@ def bench_grid(args, wl_name):
                 log("[bench] skip m=%d %s: %s" % (m, mode_name, e))
                 continue
             plan.set_fusion(fusion)
+            plan.set_graph(mode_name.endswith("_graph"))
             data.copy_(torch.from_numpy(u0).to(dev))
             sched = plan.schedule(data, T, scratch)
 
@@ -334,6 +341,7 @@ def bench_grid(args, wl_name):
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
     fused = per_launch > 1 and wl.dim == 2
     tkey = {"vector": ("sweep%dd%s_m%d" % (wl.dim, "tb" if fused else "", m)),
+            "vector_graph": ("sweep%dd%s_m%d" % (wl.dim, "tb" if fused else "", m)),
             "vector_unfused": "sweep%dd_m%d" % (wl.dim, m),
             "symmetric": "sweep%dd_m%d_symmetric" % (wl.dim, m),
             "separable": "sweep%dd_m%d_separable" % (wl.dim, m),
@@ -404,7 +412,7 @@ def bench_batched(args):
     plans = [sf.Plan(w, sf.STENCIL_STAR if k == synth.STAR else sf.STENCIL_BOX)
              for k, w in zip(kinds, weights)]
     handles = [p.handle for p in plans]
-    cache = os.path.join(tempfile.mkdtemp(prefix="stencil_tune_"), "tune.txt")
+    cache = args.tune_cache or os.path.join(tempfile.mkdtemp(prefix="stencil_tune_"), "tune.txt")
 
     def reset():
         for d, u in zip(datas, u0s):
@@ -427,16 +435,18 @@ def bench_batched(args):
                                              tune_cache=cache, use_graph=True, max_m=2)
     t_tuned = run_form("persistent_graph_tuned", lambda: sf.stencil_run_batched(
         handles, datas, scr, T, tune_cache=cache, use_graph=True, max_m=2), args.steps, args.warmup)
-    log("[bench] persistent + graph, m = 1")
-    t_m1 = run_form("persistent_graph_m1", lambda: sf.stencil_run_batched(
-        handles, datas, scr, T, use_graph=True, max_m=1), args.steps, args.warmup)
+    t_m1 = None
+    if args.only_mode != "tuned":
+        log("[bench] persistent + graph, m = 1")
+        t_m1 = run_form("persistent_graph_m1", lambda: sf.stencil_run_batched(
+            handles, datas, scr, T, use_graph=True, max_m=1), args.steps, args.warmup)
     stream = torch.cuda.current_stream(dev)
 
     def per_grid():
         for p, d, s in zip(plans, datas, scr):
             sf.stencil_run(p.handle, d, T, s, stream)
     t_pg = None
-    if not args.no_per_grid:
+    if not args.no_per_grid and args.only_mode != "tuned":
         log("[bench] per-grid launches (4096 x stencil_run, m = 1)")
         t_pg = run_form("per_grid_launches_m1", per_grid, 1, 0)
     # correctness of the headline form: mass of every grid after one run
@@ -449,19 +459,46 @@ def bench_batched(args):
         expect = math.fsum(float(v) for v in w32.ravel()) ** T * s0[i]
         drift = max(drift, abs(sf.stencil_residual(datas[i])[0] - expect) / abs(expect))
     ms = chosen["tuned"]
-    # headline kernel: the persistent sweep; algorithmic bytes per launch
-    # = every participating grid read and written once
-    sweeps = [(T // m + T % m) if m > 1 else T for m in ms]
-    launches = max(sweeps)
-    bytes_total = sum(2 * 4 * int(s) * int(s) * sw for s, sw in zip(sides, sweeps))
-    per_launch_ms = t_tuned * 1e3 / launches
-    roof = {"bound": "hbm", "achieved": round(bytes_total / launches / (per_launch_ms / 1e3) / 1e9, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    # The time loop is one graph of fused passes (several applications per
+    # launch, grids of >= 256 columns), one-step launches and a copy back of
+    # grids with an odd launch count, so its work is accounted over the whole
+    # run: algorithmic bytes = every grid read and written once per launch
+    # that passes over it (the library reports these per grid), algorithmic
+    # flops = 2 x taps x points x applications (folded and plain).
+    _, passes = sf.stencil_run_batched(handles, datas, scr, T, tune_cache=cache, use_graph=True,
+                                       max_m=2, return_passes=True)
+    taps_of = {}  # (stencil kind, m) -> nonzero taps of the operator applied
+    bytes_total = flops_total = 0
+    for p, k, s, m, ps in zip(plans, kinds, sides, ms, passes):
+        for mm in {1, m}:
+            if (k, mm) not in taps_of:
+                probe = sf.Plan(p.fold(1), sf.STENCIL_STAR if k == synth.STAR else sf.STENCIL_BOX)
+                taps_of[(k, mm)] = int(np.count_nonzero(probe.fold(mm)))
+                probe.close()
+        n2 = int(s) * int(s)
+        apps_f, apps_p = (T // m, T % m) if m > 1 else (0, T)
+        flops_total += 2 * n2 * (apps_f * taps_of[(k, m)] + apps_p * taps_of[(k, 1)])
+        bytes_total += 2 * 4 * n2 * ps
+    run_s = t_tuned
+    gbs = bytes_total / run_s / 1e9
+    tfl = flops_total / run_s / 1e12
+    if gbs / HBM_PEAK_GBS >= tfl / FP32_FMA_TFLOPS:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_FMA_TFLOPS,
+                "unit": "TFLOP/s", "peak_basis": FP32_FMA_BASIS,
+                "frac_of_published_fp32_vector": round(tfl / FP32_VECTOR_TFLOPS, 4)}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = traffic_from_profiles("batched", "batched")
-    roof["kernel"] = "k_batched (persistent, per-tile variant dispatch)"
-    roof["launch_ms"] = round(per_launch_ms, 5)
-    roof["algorithmic_bytes_per_launch"] = int(bytes_total / launches)
+    roof["traffic"] = traffic_from_profiles("batched", "batched", "hbm-bytes-per-run")
+    roof["traffic_unit"] = "HBM bytes per run (PMC FETCH_SIZE + WRITE_SIZE, calibrated)"
+    roof["kernel"] = ("whole time loop: k_batched_tb fused passes + k_batched one-step "
+                      "launches + copy back (one hipGraph)")
+    roof["run_ms"] = round(run_s * 1e3, 4)
+    roof["algorithmic_bytes_per_run"] = int(bytes_total)
+    roof["algorithmic_flops_per_run"] = int(flops_total)
+    roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+    roof["alu_frac"] = round(tfl / FP32_FMA_TFLOPS, 4)
+    roof["passes_per_grid_mean"] = round(sum(passes) / len(passes), 3)
     res = {
         "metric": METRIC,
         "value": forms["persistent_graph_tuned"]["gstencil_s"],
@@ -476,8 +513,10 @@ def bench_batched(args):
                    "fold_m_histogram": {str(m): int(sum(1 for x in ms if x == m)) for m in sorted(set(ms))}},
         "roofline": roof,
         "forms": forms,
+        "taps": {"%s_m%d" % ("star" if k == synth.STAR else "box", m): t
+                 for (k, m), t in sorted(taps_of.items())},
         "speedup_vs_per_grid_launches": round(t_pg / t_tuned, 2) if t_pg else None,
-        "speedup_tuned_vs_m1": round(t_m1 / t_tuned, 3),
+        "speedup_tuned_vs_m1": round(t_m1 / t_tuned, 3) if t_m1 else None,
         "mass_rel_drift_max_64_grids": drift,
     }
     for p in plans:

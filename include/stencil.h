@@ -84,6 +84,10 @@ typedef struct {
                              hipGraph and replay it                           */
   int max_m;              /* largest fold depth the tuner may choose (>= 1)   */
   int *chosen_m;          /* out, nullable: count entries, fold depth used    */
+  int *passes;            /* out, nullable: count entries, the launches per run
+                             that read and write grid i once each (a fused
+                             pass of several applications counts one; the
+                             copy back of an odd count is not included)      */
 } stencil_batch_opts;
 
 /*
@@ -157,6 +161,18 @@ int stencil_plan_set_mode(stencil_plan p, int mode);
  * Errors: E_ARG.  No device work.
  */
 int stencil_plan_set_fusion(stencil_plan p, int max_steps);
+
+/*
+ * stencil_plan_set_graph -- 1 = stencil_run records the launches of a
+ * periodic run (the time loop of Section 1: floor(T/m) folded and T mod m
+ * plain applications, plus the final copy of an odd launch count) once in a
+ * hipGraph, captured on a private stream, and replays it on g->stream; the
+ * graph is kept per (data, scratch, shape, dtype, T) and dropped when the
+ * plan changes (fold depth, mode, fusion, floor).  Results equal the direct
+ * launches bit for bit.  Zero-boundary runs always launch directly.
+ * 0 = launch directly (default).  Errors: E_ARG.  No device work.
+ */
+int stencil_plan_set_graph(stencil_plan p, int on);
 
 /*
  * stencil_plan_separable -- rank of the plan's current 2D operator (W_m, or

@@ -31,7 +31,8 @@ STENCIL_E_STATE = -5
 # Symbols include/stencil.h declares.
 EXPORTS = (
     "stencil_plan_create", "stencil_fold_weights", "stencil_fold_weights_f32",
-    "stencil_plan_set_mode", "stencil_plan_set_fusion", "stencil_plan_separable",
+    "stencil_plan_set_mode", "stencil_plan_set_fusion", "stencil_plan_set_graph",
+    "stencil_plan_separable",
     "stencil_plan_set_floor", "stencil_life", "stencil_life_launches",
     "stencil_plan_info",
     "stencil_profitability", "stencil_run", "stencil_run_schedule", "stencil_run_batched", "stencil_residual",
@@ -57,6 +58,7 @@ class stencil_batch_opts(ctypes.Structure):
         ("use_graph", ctypes.c_int),
         ("max_m", ctypes.c_int),
         ("chosen_m", ctypes.POINTER(ctypes.c_int)),
+        ("passes", ctypes.POINTER(ctypes.c_int)),
     ]
 
 
@@ -88,6 +90,7 @@ def _load() -> ctypes.CDLL:
     lib.stencil_fold_weights_f32.argtypes = [P, fp, i64p]
     lib.stencil_plan_set_mode.argtypes = [P, ctypes.c_int]
     lib.stencil_plan_set_fusion.argtypes = [P, ctypes.c_int]
+    lib.stencil_plan_set_graph.argtypes = [P, ctypes.c_int]
     lib.stencil_plan_separable.argtypes = [P, ip, ip]
     lib.stencil_plan_set_floor.argtypes = [P, P, ctypes.c_int, ctypes.c_int64]
     lib.stencil_life.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, P]
@@ -161,6 +164,10 @@ def stencil_plan_set_mode(plan, mode: int) -> None:
 
 def stencil_plan_set_fusion(plan, max_steps: int) -> None:
     _check(lib.stencil_plan_set_fusion(plan, max_steps))
+
+
+def stencil_plan_set_graph(plan, on: bool) -> None:
+    _check(lib.stencil_plan_set_graph(plan, int(bool(on))))
 
 
 def stencil_plan_separable(plan):
@@ -270,7 +277,9 @@ def stencil_run_schedule(plan, shape, dtype: int, T: int, data_ptr: int,
 
 def stencil_run_batched(plans, datas, scratches, T: int, autotune: bool = False,
                         tune_cache: str | None = None, use_graph: bool = True,
-                        max_m: int = 1, stream=None):
+                        max_m: int = 1, stream=None, return_passes: bool = False):
+    """Advance every grid by T steps; returns the fold depth used per grid
+    (and, with return_passes, the launches that read and write each grid)."""
     count = len(datas)
     PArr = ctypes.c_void_p * count
     parr = PArr(*[p.value if isinstance(p, ctypes.c_void_p) else p for p in plans])
@@ -283,7 +292,11 @@ def stencil_run_batched(plans, datas, scratches, T: int, autotune: bool = False,
     opts.use_graph = int(use_graph)
     opts.max_m = int(max_m)
     opts.chosen_m = ctypes.cast(chosen, ctypes.POINTER(ctypes.c_int))
+    passes = (ctypes.c_int * count)()
+    opts.passes = ctypes.cast(passes, ctypes.POINTER(ctypes.c_int))
     _check(lib.stencil_run_batched(parr, garr, count, int(T), ctypes.byref(opts)))
+    if return_passes:
+        return list(chosen), list(passes)
     return list(chosen)
 
 
@@ -331,6 +344,9 @@ class Plan:
 
     def set_fusion(self, max_steps: int) -> None:
         stencil_plan_set_fusion(self.handle, max_steps)
+
+    def set_graph(self, on: bool) -> None:
+        stencil_plan_set_graph(self.handle, on)
 
     def separable(self):
         return stencil_plan_separable(self.handle)

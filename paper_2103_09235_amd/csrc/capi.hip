@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <sstream>
+#include <string>
 
 #include "internal.h"
 
@@ -53,15 +55,21 @@ void free_operator(OperatorDev &op) {
   op = OperatorDev();
 }
 
+// The plan's run graphs on the current device.  A run using one must not be
+// in flight (plans are not mutated while their work is in flight).
+void drop_graphs(DeviceState &d) {
+  for (auto &kv : d.graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto &kv : d.graph_src) (void)hipGraphDestroy(kv.second);
+  d.graphs.clear();
+  d.graph_src.clear();
+}
+
 void free_device_state(DeviceState &d) {
   free_operator(d.plain32);
   free_operator(d.plain64);
   free_operator(d.fold32);
   free_operator(d.fold64);
-  for (auto &kv : d.graphs) (void)hipGraphExecDestroy(kv.second);
-  for (auto &kv : d.graph_src) (void)hipGraphDestroy(kv.second);
-  d.graphs.clear();
-  d.graph_src.clear();
+  drop_graphs(d);
   if (d.scratch) (void)hipFree(d.scratch);
   d.scratch = nullptr;
   d.scratch_bytes = 0;
@@ -161,6 +169,8 @@ int ensure_operators(stencil_plan p, int device, int dtype) {
     d.ready32 = d.ready64 = false;
     d.ready_m = p->m;
   }
+  // graphs hold the operators' device pointers and weights
+  if ((dtype == STENCIL_F32 && !d.ready32) || (dtype == STENCIL_F64 && !d.ready64)) drop_graphs(d);
   const int R = p->m * p->r;
   if (dtype == STENCIL_F32 && !d.ready32) {
     std::vector<float> w32(p->w.size());
@@ -219,6 +229,14 @@ void free_plan_devices(stencil_plan_s *p) {
   for (auto &kv : p->dev)
     if (hipSetDevice(kv.first) == hipSuccess) free_device_state(kv.second);
   p->dev.clear();
+  if (have) (void)hipSetDevice(cur);
+}
+
+void drop_plan_graphs(stencil_plan_s *p) {
+  int cur = 0;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  for (auto &kv : p->dev)
+    if (!kv.second.graphs.empty() && hipSetDevice(kv.first) == hipSuccess) drop_graphs(kv.second);
   if (have) (void)hipSetDevice(cur);
 }
 
@@ -308,6 +326,7 @@ int stencil_fold_weights(stencil_plan p, int m, double *out_or_null,
   } catch (...) {
     return fail(STENCIL_E_NOMEM, "host allocation failed");
   }
+  drop_plan_graphs(p);
   p->m = m;
   p->Wm.swap(Wm);
   p->Wm32.swap(W32);
@@ -339,6 +358,7 @@ int stencil_plan_set_mode(stencil_plan p, int mode) {
     return fail(STENCIL_E_UNSUPPORTED, "SEPARABLE mode needs a 2D plan");
   if (mode == STENCIL_MODE_MFMA_BF16X3 && p->dim != 2)
     return fail(STENCIL_E_UNSUPPORTED, "MFMA mode needs a 2D plan");
+  drop_plan_graphs(p);
   p->mode = mode;
   return STENCIL_OK;
 }
@@ -361,6 +381,7 @@ int stencil_plan_set_floor(stencil_plan p, const void *floor, int dtype, int64_t
   set_error("");
   if (int rc = check_plan(p)) return rc;
   if (!floor) {
+    drop_plan_graphs(p);
     p->floor = nullptr;
     p->floor_count = 0;
     return STENCIL_OK;
@@ -372,6 +393,7 @@ int stencil_plan_set_floor(stencil_plan p, const void *floor, int dtype, int64_t
     return fail(STENCIL_E_UNSUPPORTED, "a floor needs a 1D plan of radius <= 8");
   if (p->boundary != STENCIL_PERIODIC)
     return fail(STENCIL_E_UNSUPPORTED, "a floor needs periodic boundaries");
+  drop_plan_graphs(p);
   p->floor = floor;
   p->floor_dtype = dtype;
   p->floor_count = count;
@@ -443,7 +465,17 @@ int stencil_plan_set_fusion(stencil_plan p, int max_steps) {
   set_error("");
   if (int rc = check_plan(p)) return rc;
   if (max_steps < 0) return fail(STENCIL_E_ARG, "max_steps must be >= 0");
+  drop_plan_graphs(p);
   p->max_fuse = max_steps;
+  return STENCIL_OK;
+}
+
+int stencil_plan_set_graph(stencil_plan p, int on) {
+  set_error("");
+  if (int rc = check_plan(p)) return rc;
+  if (on != 0 && on != 1) return fail(STENCIL_E_ARG, "on must be 0 or 1");
+  if (!on) drop_plan_graphs(p);
+  p->use_graph = on;
   return STENCIL_OK;
 }
 
@@ -653,6 +685,48 @@ int run_dirichlet(stencil_plan p, stencil_grid *g, int64_t T, const Geom &geo, D
   return STENCIL_OK;
 }
 
+// The launches of a periodic run on stream s: the schedule's applications,
+// the two buffers alternating, and the final copy of an odd launch count.
+int enqueue_run(stencil_plan p, const Geom &geo, int dtype, const void *data, void *scratch,
+                int64_t T, DeviceState &d, hipStream_t s) {
+  const size_t bytes = (size_t)geo.count() * esize(dtype);
+  const OperatorDev *ops[2] = {dtype == STENCIL_F32 ? &d.fold32 : &d.fold64,
+                               dtype == STENCIL_F32 ? &d.plain32 : &d.plain64};
+  const Schedule sc = make_schedule(p, geo, dtype, data, scratch, T);
+  SweepLaunch L;
+  L.g = geo;
+  L.dtype = dtype;
+  L.stream = s;
+  L.floor = p->floor;
+  const void *src = data;
+  void *dst = scratch;
+  for (int i = 0; i < 2; ++i) {
+    if (sc.apps[i] == 0) continue;
+    L.op = ops[i];
+    int64_t left = sc.apps[i];
+    const int64_t nl = sc.launches[i];
+    for (int64_t k = 0; k < nl; ++k) {
+      const int64_t take = (left + (nl - k) - 1) / (nl - k);
+      L.in = src;
+      L.out = dst;
+      L.steps = (int)take;
+      hipError_t e = dispatch(p, L);
+      if (e != hipSuccess) return hip_fail(e, "sweep launch");
+      left -= take;
+      const void *t = src;
+      src = dst;
+      dst = const_cast<void *>(t);
+    }
+  }
+  if (src != data) {
+    hipError_t e = launch_copy(src, const_cast<void *>(data), (int64_t)bytes, s);
+    if (e != hipSuccess) return hip_fail(e, "final copy");
+  }
+  return STENCIL_OK;
+}
+
+constexpr size_t kMaxRunGraphs = 16;  // per plan and device
+
 }  // namespace
 }  // namespace stencil
 
@@ -695,6 +769,7 @@ int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
     if (d.scratch_bytes < bytes) {
       if (d.scratch) {
         STENCIL_HIP_TRY(hipDeviceSynchronize());
+        drop_graphs(d);
         (void)hipFree(d.scratch);
         d.scratch = nullptr;
         d.scratch_bytes = 0;
@@ -704,38 +779,36 @@ int stencil_run(stencil_plan p, stencil_grid *g, int64_t T) {
     }
     scratch = d.scratch;
   }
-  const OperatorDev *ops[2] = {g->dtype == STENCIL_F32 ? &d.fold32 : &d.fold64,
-                               g->dtype == STENCIL_F32 ? &d.plain32 : &d.plain64};
-  const Schedule sc = make_schedule(p, geo, g->dtype, g->data, scratch, T);
-  SweepLaunch L;
-  L.g = geo;
-  L.dtype = g->dtype;
-  L.stream = (hipStream_t)g->stream;
-  L.floor = p->floor;
-  const void *src = g->data;
-  void *dst = scratch;
-  for (int i = 0; i < 2; ++i) {
-    if (sc.apps[i] == 0) continue;
-    L.op = ops[i];
-    int64_t left = sc.apps[i];
-    const int64_t nl = sc.launches[i];
-    for (int64_t k = 0; k < nl; ++k) {
-      const int64_t take = (left + (nl - k) - 1) / (nl - k);
-      L.in = src;
-      L.out = dst;
-      L.steps = (int)take;
-      hipError_t e = dispatch(p, L);
-      if (e != hipSuccess) return hip_fail(e, "sweep launch");
-      left -= take;
-      const void *t = src;
-      src = dst;
-      dst = const_cast<void *>(t);
+  if (!p->use_graph) return enqueue_run(p, geo, g->dtype, g->data, scratch, T, d,
+                                        (hipStream_t)g->stream);
+  // the run's launches captured once per (data, scratch, shape, dtype, T)
+  std::ostringstream ks;
+  ks << g->data << ":" << scratch << ":" << geo.nz << "x" << geo.ny << "x" << geo.nx << ":"
+     << g->dtype << ":" << T;
+  const std::string key = ks.str();
+  auto it = d.graphs.find(key);
+  if (it == d.graphs.end()) {
+    if (d.graphs.size() >= kMaxRunGraphs) drop_graphs(d);
+    hipStream_t cs = nullptr;
+    STENCIL_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int rc = STENCIL_OK;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      rc = enqueue_run(p, geo, g->dtype, g->data, scratch, T, d, cs);
+      e = hipStreamEndCapture(cs, &graph);
     }
+    if (e == hipSuccess && rc == STENCIL_OK) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (rc != STENCIL_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc != STENCIL_OK ? rc : hip_fail(e, "run graph capture");
+    }
+    d.graph_src[key] = graph;
+    it = d.graphs.emplace(key, exec).first;
   }
-  if (src != g->data) {
-    hipError_t e = launch_copy(src, g->data, (int64_t)bytes, L.stream);
-    if (e != hipSuccess) return hip_fail(e, "final copy");
-  }
+  STENCIL_HIP_TRY(hipGraphLaunch(it->second, (hipStream_t)g->stream));
   return STENCIL_OK;
 }
 

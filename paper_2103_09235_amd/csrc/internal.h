@@ -75,6 +75,7 @@ struct DeviceState {
 struct stencil_plan_s {
   int dim = 0, r = 0, shape = 0, boundary = 0, mode = STENCIL_MODE_VECTOR;
   int max_fuse = 0;           // steps one launch may fuse; 0 = library choice
+  int use_graph = 0;          // 1 = replay periodic runs from captured hipGraphs
   const void *floor = nullptr;  // caller's floor array (device), or none
   int floor_dtype = 0;
   int64_t floor_count = 0;
@@ -91,6 +92,8 @@ namespace stencil {
 
 // Free every device resource a plan holds (all devices); the plan stays valid.
 void free_plan_devices(stencil_plan_s *p);
+// Drop the captured run graphs of a plan (all devices).
+void drop_plan_graphs(stencil_plan_s *p);
 
 int side_of(int R);
 int64_t count_of(int dim, int R);

@@ -98,6 +98,10 @@ def test_plan_info_mode_and_profitability():
     with pytest.raises(sf.StencilError) as e:
         p.set_fusion(-1)
     assert e.value.code == sf.STENCIL_E_ARG
+    p.set_graph(True)
+    p.set_graph(False)
+    assert sf.lib.stencil_plan_set_graph(p.handle, 2) == sf.STENCIL_E_ARG
+    assert sf.lib.stencil_plan_set_graph(None, 1) == sf.STENCIL_E_ARG
 
 
 def test_plan_f32_weights_start_unfolded():

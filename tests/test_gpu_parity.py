@@ -639,3 +639,71 @@ def test_batched_fused_passes_bit_exact(tmp_path, T, m):
     assert chosen == [m] * len(grids)
     for g, w, o in zip(grids, weights, outs):
         assert np.array_equal(o, oracle.folded_reference_f32(w, g, T, m))
+
+
+GRAPH_CASES = [
+    # (name, weights, kind, shape, T, m, mode, dtype, caller scratch)
+    ("star2d_fused_odd", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (300, 1024), 37, 1,
+     "vector", np.float32, True),
+    ("star2d_m4_plan_scratch", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (257, 1031), 14,
+     4, "vector", np.float32, False),
+    ("box2d_m8_mfma", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (140, 530), 16, 8, "mfma",
+     np.float32, True),
+    ("heat1d_f64", synth.heat1d_weights(), sf.STENCIL_STAR, (100_003,), 37, 1, "vector", np.float64,
+     True),
+    ("star3d_m2", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (20, 33, 70), 7, 2, "vector",
+     np.float32, True),
+    ("box2d_exact", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (61, 99), 5, 1, "exact",
+     np.float32, False),
+]
+
+
+@pytest.mark.parametrize("case", GRAPH_CASES, ids=lambda c: c[0])
+def test_run_graph_replays_equal_direct_launches(case):
+    """stencil_plan_set_graph: the captured time loop, replayed several times
+    with other eager work and synchronisations in between, gives the direct
+    launches' result bit for bit every time (and the oracle's where the
+    kernels keep the canonical order)."""
+    name, w, kind, shape, T, m, mode, dt, caller_scratch = case
+    w = synth.to_f32_exact(w) if dt == np.float32 else w
+    u0 = synth.grid_f32(shape) if dt == np.float32 else synth.grid_f64(shape)
+    print("graph replay", name, shape, "T", T, "m", m, mode, flush=True)
+    modes = {"vector": sf.STENCIL_MODE_VECTOR, "exact": sf.STENCIL_MODE_EXACT_ORDER,
+             "mfma": sf.STENCIL_MODE_MFMA_BF16X3}
+    plan = sf.Plan(w, kind)
+    if m > 1:
+        plan.fold(m)
+    plan.set_mode(modes[mode])
+    data = torch.from_numpy(u0).to(DEV)
+    scr = torch.empty_like(data) if caller_scratch else None
+    plan.run(data, T, scr)
+    torch.cuda.synchronize()
+    direct = data.cpu().numpy()
+    if mode != "mfma":
+        ref = (oracle.folded_reference_f32(w, u0, T, m) if dt == np.float32
+               else oracle.sweep(w, u0, T))
+        assert np.array_equal(direct, ref)
+    plan.set_graph(True)
+    other = sf.Plan(synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR)
+    side = torch.from_numpy(synth.grid_f32((64, 80), stream=7)).to(DEV)
+    for rep in range(4):
+        data.copy_(torch.from_numpy(u0).to(DEV))
+        plan.run(data, T, scr)
+        # eager work of the program between replays
+        other.run(side, 3)
+        _ = (side * 2.0).sum().item()
+        torch.cuda.synchronize()
+        assert np.array_equal(data.cpu().numpy(), direct), "replay %d differs" % rep
+    # a plan change drops the graph: fold depth 1 must give the plain result
+    plan.fold(1)
+    data.copy_(torch.from_numpy(u0).to(DEV))
+    plan.run(data, T, scr)
+    torch.cuda.synchronize()
+    plain = data.cpu().numpy()
+    plan.set_graph(False)
+    data.copy_(torch.from_numpy(u0).to(DEV))
+    plan.run(data, T, scr)
+    torch.cuda.synchronize()
+    assert np.array_equal(plain, data.cpu().numpy())
+    other.close()
+    plan.close()
