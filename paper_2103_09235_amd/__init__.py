@@ -6,4 +6,4 @@ it fails loudly if the library has not been built.
 """
 
 from .binding import *  # noqa: F401,F403
-from .binding import Plan, StencilError, make_grid, lib, LIB_PATH, EXPORTS  # noqa: F401
+from .binding import Plan, BatchedRun, StencilError, make_grid, lib, LIB_PATH, EXPORTS  # noqa: F401

@@ -275,29 +275,45 @@ def stencil_run_schedule(plan, shape, dtype: int, T: int, data_ptr: int,
             "plain_launches": out[3], "final_copy": bool(copy.value)}
 
 
+class BatchedRun:
+    """The arguments of stencil_run_batched marshalled once (plan handles,
+    grid descriptors of the data and scratch tensors, stream) for repeated
+    runs of one batch; the tensors are kept alive with it."""
+
+    def __init__(self, plans, datas, scratches, stream=None):
+        self.count = len(datas)
+        self._tensors = (list(datas), list(scratches))
+        self.parr = (ctypes.c_void_p * self.count)(
+            *[p.value if isinstance(p, ctypes.c_void_p) else p for p in plans])
+        self.garr = (stencil_grid * self.count)(
+            *[make_grid(d, s, stream) for d, s in zip(datas, scratches)])
+        self.chosen = (ctypes.c_int * self.count)()
+        self.passes = (ctypes.c_int * self.count)()
+
+    def run(self, T: int, autotune: bool = False, tune_cache: str | None = None,
+            use_graph: bool = True, max_m: int = 1):
+        """Advance every grid by T steps; returns the fold depth used per grid."""
+        opts = stencil_batch_opts()
+        opts.autotune = int(autotune)
+        opts.tune_cache = tune_cache.encode() if tune_cache else None
+        opts.use_graph = int(use_graph)
+        opts.max_m = int(max_m)
+        opts.chosen_m = ctypes.cast(self.chosen, ctypes.POINTER(ctypes.c_int))
+        opts.passes = ctypes.cast(self.passes, ctypes.POINTER(ctypes.c_int))
+        _check(lib.stencil_run_batched(self.parr, self.garr, self.count, int(T), ctypes.byref(opts)))
+        return list(self.chosen)
+
+
 def stencil_run_batched(plans, datas, scratches, T: int, autotune: bool = False,
                         tune_cache: str | None = None, use_graph: bool = True,
                         max_m: int = 1, stream=None, return_passes: bool = False):
     """Advance every grid by T steps; returns the fold depth used per grid
     (and, with return_passes, the launches that read and write each grid)."""
-    count = len(datas)
-    PArr = ctypes.c_void_p * count
-    parr = PArr(*[p.value if isinstance(p, ctypes.c_void_p) else p for p in plans])
-    GArr = stencil_grid * count
-    garr = GArr(*[make_grid(d, s, stream) for d, s in zip(datas, scratches)])
-    chosen = (ctypes.c_int * count)()
-    opts = stencil_batch_opts()
-    opts.autotune = int(autotune)
-    opts.tune_cache = tune_cache.encode() if tune_cache else None
-    opts.use_graph = int(use_graph)
-    opts.max_m = int(max_m)
-    opts.chosen_m = ctypes.cast(chosen, ctypes.POINTER(ctypes.c_int))
-    passes = (ctypes.c_int * count)()
-    opts.passes = ctypes.cast(passes, ctypes.POINTER(ctypes.c_int))
-    _check(lib.stencil_run_batched(parr, garr, count, int(T), ctypes.byref(opts)))
+    br = BatchedRun(plans, datas, scratches, stream)
+    chosen = br.run(T, autotune=autotune, tune_cache=tune_cache, use_graph=use_graph, max_m=max_m)
     if return_passes:
-        return list(chosen), list(passes)
-    return list(chosen)
+        return chosen, list(br.passes)
+    return chosen
 
 
 def stencil_residual(u, ref=None, stream=None):

@@ -62,6 +62,7 @@ struct Tile {
 __host__ __device__ constexpr int variant_id(int R, bool diamond, bool vx4) {
   return (R - 1) * 4 + (diamond ? 2 : 0) + (vx4 ? 1 : 0);
 }
+__host__ __device__ constexpr bool variant_diamond(int var) { return (var & 2) != 0; }
 
 // Variants: aligned rows of >= 256 floats use vector lanes (two rows of
 // look-ahead), the rest strided lanes (4 coalesced scalars per lane).
@@ -146,12 +147,18 @@ __device__ __forceinline__ float tb_from_right(float x) {
 __host__ __device__ constexpr int tb_border(int K, int R) { return (K * R + 3) / 4 * 4; }
 __host__ __device__ constexpr int tb_kmax(int R) { return R == 1 ? 8 : 4; }
 
-// VEC: rows of whole 16-byte vectors (one vector load and store per lane and
-// row); otherwise four scalar loads, each column wrapped on its own, and
-// stores column by column.
-template <int R, int MASK, bool VEC, bool FULL>
+// VX columns per lane (4, 2 or 1: strips of 256, 128 or 64 columns; the
+// narrow ones cover a grid's last columns, or a whole narrow grid, with less
+// discarded border work); VX >= R, so a neighbour column is at most one lane
+// away.  VEC (VX = 4 only): rows of whole 16-byte vectors (one vector load
+// and store per lane and row); otherwise VX scalar loads, each column wrapped
+// on its own, and stores column by column.  The strip's columns must span
+// less than twice the grid's width (each column wraps at most once):
+// 64 * VX - B - 2 < nx.
+template <int R, int MASK, int VX, bool VEC, bool FULL>
 __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, int ny, int nx,
                          int xo0, int y0, int y1, int Kr, const float *__restrict__ wt) {
+  static_assert(VX >= R && (!VEC || VX == 4), "strip layout");
   using k2d::fmat;
   using k2d::in_mask;
   using k2d::load_vec;
@@ -161,43 +168,43 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
   constexpr int NU = S;
   constexpr int KMAX = tb_kmax(R);
   constexpr int B = tb_border(KMAX, R);
-  constexpr int WOUT = 256 - 2 * B;
+  constexpr int WOUT = 64 * VX - 2 * B;
   const int K = FULL ? KMAX : Kr;
   float W[S * S];
 #pragma unroll
   for (int i = 0; i < S * S; ++i) W[i] = wt[i];
   const int lane = threadIdx.x;
-  const int gx = wrap1(xo0 - B + 4 * lane, nx);
-  int gxs[4];  // scalar path: each column wrapped on its own
+  const int gx = wrap1(xo0 - B + VX * lane, nx);
+  int gxs[VX];  // scalar path: each column wrapped on its own
 #pragma unroll
-  for (int v = 0; v < 4; ++v) gxs[v] = wrap1(xo0 - B + 4 * lane + v, nx);
-  const int lo = 4 * lane - B;
-  const bool store_ok = lo >= 0 && lo + 4 <= WOUT && xo0 + lo + 4 <= nx;
-  bool store_v[4];
+  for (int v = 0; v < VX; ++v) gxs[v] = wrap1(xo0 - B + VX * lane + v, nx);
+  const int lo = VX * lane - B;
+  const bool store_ok = lo >= 0 && lo + VX <= WOUT && xo0 + lo + VX <= nx;
+  bool store_v[VX];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) store_v[v] = lo + v >= 0 && lo + v < WOUT && xo0 + lo + v < nx;
+  for (int v = 0; v < VX; ++v) store_v[v] = lo + v >= 0 && lo + v < WOUT && xo0 + lo + v < nx;
   const int jstart = y0 - K * R, jend = y1 + K * R;
-  float acc[KMAX][NU][4];
+  float acc[KMAX][NU][VX];
 #pragma unroll
   for (int st = 0; st < KMAX; ++st)
 #pragma unroll
     for (int k = 0; k < NU; ++k)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[st][k][v] = 0.0f;
-  auto row = [&](const int j, const int u, const float (&in_row)[4]) {
-    float cur[4], res[4];
+      for (int v = 0; v < VX; ++v) acc[st][k][v] = 0.0f;
+  auto row = [&](const int j, const int u, const float (&in_row)[VX]) {
+    float cur[VX], res[VX];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) cur[v] = res[v] = in_row[v];
+    for (int v = 0; v < VX; ++v) cur[v] = res[v] = in_row[v];
 #pragma unroll
     for (int st = 0; st < KMAX; ++st) {
       {
-        float win[4 + 2 * R];
+        float win[VX + 2 * R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) win[i] = tb_from_left(cur[4 - R + i]);
+        for (int i = 0; i < R; ++i) win[i] = tb_from_left(cur[VX - R + i]);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) win[R + v] = cur[v];
+        for (int v = 0; v < VX; ++v) win[R + v] = cur[v];
 #pragma unroll
-        for (int i = 0; i < R; ++i) win[R + 4 + i] = tb_from_right(cur[i]);
+        for (int i = 0; i < R; ++i) win[R + VX + i] = tb_from_right(cur[i]);
 #pragma unroll
         for (int k = S - 1; k >= 0; --k) {
           const int slot = (u + k) % NU;
@@ -208,33 +215,33 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
               const float w = W[(oy + R) * S + (ox + R)];
               const bool first = k == S - 1 && ox == (MASK == MASK_BOX ? -R : 0);
 #pragma unroll
-              for (int v = 0; v < 4; ++v)
+              for (int v = 0; v < VX; ++v)
                 acc[st][slot][v] = fmat(w, win[R + v + ox], first ? 0.0f : acc[st][slot][v]);
             }
           }
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) cur[v] = acc[st][u % NU][v];
+        for (int v = 0; v < VX; ++v) cur[v] = acc[st][u % NU][v];
         if constexpr (!FULL) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) res[v] = st == K - 1 ? cur[v] : res[v];
+          for (int v = 0; v < VX; ++v) res[v] = st == K - 1 ? cur[v] : res[v];
         }
       }
     }
     const int yd = j - K * R;
     if (yd >= y0 && yd < y1) {
       float *dst = out + (size_t)yd * nx + xo0 + lo;
-      const float(&val)[4] = FULL ? cur : res;
+      const float(&val)[VX] = FULL ? cur : res;
       if constexpr (VEC) {
         if (store_ok) store_vec<float, 4>(dst, val);
       } else {
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < VX; ++v)
           if (store_v[v]) dst[v] = val[v];
       }
     }
   };
-  auto fetch = [&](const int j0, float (&buf)[NU][4]) {
+  auto fetch = [&](const int j0, float (&buf)[NU][VX]) {
 #pragma unroll
     for (int p = 0; p < NU; ++p) {
       const float *rowp = in + (size_t)wrap1(min(j0 + p, jend - 1), ny) * nx;
@@ -242,11 +249,11 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
         load_vec<float, 4>(rowp + gx, buf[p]);
       } else {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) buf[p][v] = rowp[gxs[v]];
+        for (int v = 0; v < VX; ++v) buf[p][v] = rowp[gxs[v]];
       }
     }
   };
-  float bufA[NU][4], bufB[NU][4];
+  float bufA[NU][VX], bufB[NU][VX];
   fetch(jstart, bufA);
   for (int jb = jstart; jb < jend; jb += 2 * NU) {
     fetch(jb + NU, bufB);
@@ -262,7 +269,7 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
 // One kernel per radius and row layout, so that each gets its own register
 // allocation (a kernel holding every variant would run all of them at the
 // occupancy of the largest).
-template <int R, bool VEC>
+template <int R, int VX, bool VEC>
 __global__ void __launch_bounds__(64)
 k_batched_tb(const Tile *__restrict__ tiles, const GridInfo *__restrict__ grids,
              const float *__restrict__ wtab, int k) {
@@ -279,18 +286,31 @@ k_batched_tb(const Tile *__restrict__ tiles, const GridInfo *__restrict__ grids,
   const float *in = (k & 1) ? g.scratch : g.data;
   float *out = (k & 1) ? g.data : g.scratch;
   const float *w = wtab + g.w_f;
-  const bool dia = g.var_f == variant_id(R, true, VEC);
+  const bool dia = variant_diamond(g.var_f);
   if (K == KMAX) {
-    if (dia) tb_strip<R, MASK_DIAMOND, VEC, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
-    else tb_strip<R, MASK_BOX, VEC, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
+    if (dia) tb_strip<R, MASK_DIAMOND, VX, VEC, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
+    else tb_strip<R, MASK_BOX, VX, VEC, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
   } else {
-    if (dia) tb_strip<R, MASK_DIAMOND, VEC, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
-    else tb_strip<R, MASK_BOX, VEC, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
+    if (dia) tb_strip<R, MASK_DIAMOND, VX, VEC, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
+    else tb_strip<R, MASK_BOX, VX, VEC, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
   }
 }
 
-// tile groups of the fused passes: (R - 1) * 2 + VEC
-constexpr int kTbGroups = 4;
+// Strip layouts of the fused passes, and their tile groups: group =
+// (R - 1) * kTbLayouts + layout (radius 2 has no one-column layout).
+enum TbLayout { kTb4 = 0, kTb4Vec = 1, kTb2 = 2, kTb1 = 3, kTbLayouts = 4 };
+constexpr int kTbGroups = 2 * kTbLayouts;
+__host__ __device__ constexpr int tb_vx(int layout) {
+  return layout == kTb2 ? 2 : layout == kTb1 ? 1 : 4;
+}
+// output columns of a strip: 64 * VX lanes' columns minus the border each side
+__host__ __device__ constexpr int tb_wout(int R, int layout) {
+  return 64 * tb_vx(layout) - 2 * tb_border(tb_kmax(R), R);
+}
+// the strip's columns wrap at most once: 64 * VX - B - 2 < nx
+__host__ __device__ constexpr int tb_min_nx(int R, int layout) {
+  return 64 * tb_vx(layout) - tb_border(tb_kmax(R), R) - 1;
+}
 
 // Grids whose total sweep count is odd end in scratch: copy them back.
 __global__ void __launch_bounds__(256)
@@ -301,6 +321,49 @@ k_batched_copyback(const GridInfo *__restrict__ grids, const int *__restrict__ o
     for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
       g.data[e] = g.scratch[e];
   }
+}
+
+// Column strips (layout, first column) of a fused grid: 256-column strips
+// while whole ones fit, then the cheapest cover of the remaining columns:
+// one more wide strip, or 128-column strips followed by 64-column ones,
+// priced by their lanes' columns times a per-layout cost per column (the
+// narrow layouts spend relatively more on neighbour exchange and loop work).
+// Empty when no layout fits the grid's width (then it is not fused).
+std::vector<std::pair<int, int>> strip_plan(int nx, int R, bool vec) {
+  constexpr double kCost[kTbLayouts] = {1.0, 1.0, 1.15, 1.4};
+  std::vector<std::pair<int, int>> out;
+  const bool ok4 = nx >= tb_min_nx(R, kTb4);
+  const bool ok2 = nx >= tb_min_nx(R, kTb2);
+  const bool ok1 = R == 1 && nx >= tb_min_nx(R, kTb1);
+  const int w4 = tb_wout(R, kTb4), w2 = tb_wout(R, kTb2), w1 = tb_wout(R, kTb1);
+  const int wide = vec ? kTb4Vec : kTb4;
+  int x = 0;
+  if (ok4)
+    for (; nx - x >= w4; x += w4) out.push_back({wide, x});
+  const int rem = nx - x;
+  if (rem == 0) return out;
+  double best = ok4 ? 256 * kCost[kTb4] : 1e30;
+  int ba = -1, bb = 0;
+  const int amax = ok2 ? (rem + w2 - 1) / w2 : 0;
+  for (int a = 0; a <= amax; ++a) {
+    const int left = std::max(0, rem - a * w2);
+    if (left > 0 && !ok1) continue;
+    const int b = left > 0 ? (left + w1 - 1) / w1 : 0;
+    const double c = a * 128 * kCost[kTb2] + b * 64 * kCost[kTb1];
+    if (c < best) {
+      best = c;
+      ba = a;
+      bb = b;
+    }
+  }
+  if (ba < 0) {
+    if (!ok4) return {};
+    out.push_back({wide, x});
+    return out;
+  }
+  for (int a = 0; a < ba; ++a, x += w2) out.push_back({kTb2, x});
+  for (int b = 0; b < bb; ++b, x += w1) out.push_back({kTb1, x});
+  return out;
 }
 
 // --------------------------------------------------------------- tuning
@@ -353,80 +416,13 @@ int plan_weights32(stencil_plan p, int m, const std::vector<float> *&out) {
   return STENCIL_OK;
 }
 
-// Time m = 1..max_m on a grid of the class's size with the single-grid
-// sweep, over enough original steps (a multiple of 8, about 2^27 point-steps)
-// that a run lasts far longer than the timer's noise; the fastest of three
-// runs per m is compared, and a larger m must win by 3% (ties go to the
-// smaller m).
-int tune_one(stencil_plan p, int side, int max_m, hipStream_t stream, int *best_m) {
-  const size_t bytes = (size_t)side * side * sizeof(float);
-  float *a = nullptr, *b = nullptr;
-  STENCIL_HIP_TRY(hipMalloc(&a, bytes));
-  hipError_t e = hipMalloc(&b, bytes);
-  if (e != hipSuccess) {
-    (void)hipFree(a);
-    return hip_fail(e, "tune alloc");
-  }
-  (void)hipMemsetAsync(a, 0, bytes, stream);
-  hipEvent_t e0, e1;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
-  double best = 1e30;
-  *best_m = 1;
-  int rc = STENCIL_OK;
-  for (int m = 1; m <= max_m && rc == STENCIL_OK; ++m) {
-    if (m * p->r > kMaxBatchRadius || side < 2 * m * p->r + 1) break;
-    stencil_plan_s tmp = *p;  // same weights, own fold depth and device state
-    tmp.dev.clear();
-    tmp.batch_w32.clear();
-    // time what the batch runs: VECTOR kernels, fused passes where the grid
-    // allows them (the batched passes fuse as the single-grid sweep does for
-    // radius <= 2)
-    tmp.mode = STENCIL_MODE_VECTOR;
-    tmp.max_fuse = 0;
-    rc = stencil_fold_weights(&tmp, m, nullptr, nullptr);
-    if (rc) break;
-    stencil_grid g{};
-    g.data = a;
-    g.scratch = b;
-    g.dtype = STENCIL_F32;
-    g.dim = 2;
-    g.shape[0] = g.shape[1] = side;
-    g.stream = stream;
-    const int64_t pts = (int64_t)side * side;
-    const int64_t T = std::min<int64_t>(512, std::max<int64_t>(16, ((1 << 27) / pts + 7) / 8 * 8));
-    rc = stencil_run(&tmp, &g, T);  // warm
-    float ms = 1e30f;
-    for (int rep = 0; rep < 3 && rc == STENCIL_OK; ++rep) {
-      (void)hipEventRecord(e0, stream);
-      rc = stencil_run(&tmp, &g, T);
-      (void)hipEventRecord(e1, stream);
-      (void)hipEventSynchronize(e1);
-      float t = 0.f;
-      (void)hipEventElapsedTime(&t, e0, e1);
-      ms = std::min(ms, t);
-    }
-    free_plan_devices(&tmp);
-    if (rc == STENCIL_OK && ms < best * 0.97) {  // 3% margin, ties to smaller m
-      best = ms;
-      *best_m = m;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipStreamSynchronize(stream);
-  (void)hipFree(a);
-  (void)hipFree(b);
-  return rc;
-}
-
 // ---------------------------------------------------------- batch cache
 
 struct BatchEntry {
-  std::string key;
+  std::vector<uint64_t> key;  // signature: run settings, then 6 words per grid
   int device = 0;
   Tile *d_tiles_tb = nullptr;  // fused strips (one block each), by group
-  int tb_off[kTbGroups + 1] = {0, 0, 0, 0, 0};
+  int tb_off[kTbGroups + 1] = {};
   int launches_tb = 0;
   Tile *d_tiles = nullptr;
   GridInfo *d_grids = nullptr;
@@ -463,11 +459,16 @@ hipError_t enqueue(const BatchEntry &b, hipStream_t s) {
       const int n = b.tb_off[grp + 1] - b.tb_off[grp];
       if (n == 0) continue;
       const Tile *t = b.d_tiles_tb + b.tb_off[grp];
+      const dim3 gr(n), bl(64);
       switch (grp) {
-        case 0: hipLaunchKernelGGL((k_batched_tb<1, false>), dim3(n), dim3(64), 0, s, t, b.d_grids, b.d_w, k); break;
-        case 1: hipLaunchKernelGGL((k_batched_tb<1, true>), dim3(n), dim3(64), 0, s, t, b.d_grids, b.d_w, k); break;
-        case 2: hipLaunchKernelGGL((k_batched_tb<2, false>), dim3(n), dim3(64), 0, s, t, b.d_grids, b.d_w, k); break;
-        default: hipLaunchKernelGGL((k_batched_tb<2, true>), dim3(n), dim3(64), 0, s, t, b.d_grids, b.d_w, k); break;
+        case kTb4: hipLaunchKernelGGL((k_batched_tb<1, 4, false>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
+        case kTb4Vec: hipLaunchKernelGGL((k_batched_tb<1, 4, true>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
+        case kTb2: hipLaunchKernelGGL((k_batched_tb<1, 2, false>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
+        case kTb1: hipLaunchKernelGGL((k_batched_tb<1, 1, false>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
+        case kTbLayouts + kTb4: hipLaunchKernelGGL((k_batched_tb<2, 4, false>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
+        case kTbLayouts + kTb4Vec: hipLaunchKernelGGL((k_batched_tb<2, 4, true>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
+        case kTbLayouts + kTb2: hipLaunchKernelGGL((k_batched_tb<2, 2, false>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
+        default: return hipErrorInvalidValue;  // no one-column strips at radius 2
       }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
@@ -487,6 +488,225 @@ hipError_t enqueue(const BatchEntry &b, hipStream_t s) {
     return hipGetLastError();
   }
   return hipSuccess;
+}
+
+// Builds a batch: fold weights, fused strips and one-step tiles per grid,
+// device tables, and (use_graph) the captured time loop.
+int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count, int64_t T,
+                const std::vector<int> &m_of, bool use_graph, int device, BatchEntry &b) {
+  b.device = device;
+  std::vector<GridInfo> gi(count);
+  std::vector<float> wt;
+  std::map<std::pair<stencil_plan, int>, int> woff;
+  auto weights_at = [&](stencil_plan p, int m, int *off) -> int {
+    auto f = woff.find({p, m});
+    if (f != woff.end()) {
+      *off = f->second;
+      return STENCIL_OK;
+    }
+    const std::vector<float> *w;
+    int rc = plan_weights32(p, m, w);
+    if (rc) return rc;
+    *off = (int)wt.size();
+    wt.insert(wt.end(), w->begin(), w->end());
+    woff[{p, m}] = *off;
+    return STENCIL_OK;
+  };
+  std::vector<std::pair<int64_t, Tile>> tiles, tiles_tb[kTbGroups];
+  std::vector<int> odd;
+  int launches = 0, launches_tb = 0;
+  for (int i = 0; i < count; ++i) {
+    const stencil_plan p = plans[i];
+    const stencil_grid &g = grids[i];
+    const int m = m_of[i];
+    GridInfo &G = gi[i];
+    G.data = (float *)g.data;
+    G.scratch = (float *)g.scratch;
+    G.ny = (int)g.shape[0];
+    G.nx = (int)g.shape[1];
+    G.q = m > 1 ? (int)(T / m) : 0;
+    G.s = m > 1 ? (int)(T % m) : (int)T;
+    const bool vx4 = (G.nx % 4 == 0) && ((uintptr_t)g.data % 16 == 0) &&
+                     ((uintptr_t)g.scratch % 16 == 0);
+    const bool star = p->shape == STENCIL_STAR;
+    G.var_p = variant_id(p->r, star, vx4);
+    G.var_f = variant_id(m * p->r, star, vx4);
+    int rc = weights_at(p, 1, &G.w_p);
+    if (rc) return rc;
+    G.w_f = G.w_p;
+    if (m > 1 && (rc = weights_at(p, m, &G.w_f))) return rc;
+    const int R = m * p->r;
+    // fused passes: the folded applications (the plain ones at m = 1) of
+    // grids that some strip layout fits, up to tb_kmax(R) per pass
+    G.fpass = G.nfull = G.tail = 0;
+    const std::vector<std::pair<int, int>> strips =
+        R <= kMaxBatchRadius && G.ny >= 2 * tb_kmax(R) * R + 1
+            ? strip_plan(G.nx, R, vx4) : std::vector<std::pair<int, int>>();
+    if (!strips.empty()) {
+      const int apps = m > 1 ? G.q : G.s;
+      const int rest = m > 1 ? G.s : 0;
+      const int KM = tb_kmax(R);
+      if (apps > 1) {
+        // full passes, then the remainder.  An odd launch count is not
+        // made even by splitting a pass: a pass costs about the same time
+        // whatever its K (it is bound by the strips' memory latency),
+        // more than copying the grid back
+        G.nfull = apps / KM;
+        G.tail = apps % KM;
+        G.fpass = G.nfull + (G.tail > 0);
+        G.q = 0;
+        G.s = rest;
+      }
+    }
+    const int sweeps = G.fpass + (G.fpass ? G.s : G.q + G.s);
+    b.passes.push_back(sweeps);
+    launches = std::max(launches, G.fpass ? G.s : G.q + G.s);
+    launches_tb = std::max(launches_tb, G.fpass);
+    if (sweeps % 2) odd.push_back(i);
+    if (G.fpass) {
+      const int kk = G.nfull ? tb_kmax(R) : G.tail;
+      const int rows = tb_rows();
+      for (int y0 = 0; y0 < G.ny; y0 += rows)
+        for (const auto &st : strips) {
+          const int y1 = std::min(G.ny, y0 + rows);
+          const int64_t cost = (int64_t)(y1 - y0 + 2 * kk * R) * kk * (2 * R + 1) * tb_vx(st.first);
+          tiles_tb[(R - 1) * kTbLayouts + st.first].push_back({cost, Tile{i, st.second, y0, y1}});
+        }
+    }
+    const int bx = 256;
+    const int Rp = G.fpass ? p->r : R;  // one-step work of fused grids is plain
+    if (G.fpass == 0 || G.s > 0)
+      for (int y0 = 0; y0 < G.ny; y0 += kTileRows)
+        for (int x0 = 0; x0 < G.nx; x0 += bx) {
+          const int y1 = std::min(G.ny, y0 + kTileRows);
+          const int64_t cost = (int64_t)(y1 - y0 + 2 * Rp) * (2 * Rp + 1);
+          tiles.push_back({cost, Tile{i, x0, y0, y1}});
+        }
+  }
+  auto by_cost = [](const auto &a, const auto &b) { return a.first > b.first; };
+  std::stable_sort(tiles.begin(), tiles.end(), by_cost);
+  std::vector<Tile> tl(tiles.size()), tltb;
+  for (size_t t = 0; t < tiles.size(); ++t) tl[t] = tiles[t].second;
+  for (int grp = 0; grp < kTbGroups; ++grp) {
+    // strips in grid, row band, column order (neighbours adjacent); every
+    // block is resident at once or nearly, so cost order matters little
+    static const bool by_cost_env = std::getenv("STENCIL_BATCH_TB_SORT") != nullptr;
+    if (by_cost_env) std::stable_sort(tiles_tb[grp].begin(), tiles_tb[grp].end(), by_cost);
+    b.tb_off[grp] = (int)tltb.size();
+    for (const auto &ct : tiles_tb[grp]) tltb.push_back(ct.second);
+  }
+  b.tb_off[kTbGroups] = (int)tltb.size();
+  if (tltb.size() > (size_t)((1LL << 31) - 1)) return fail(STENCIL_E_UNSUPPORTED, "batch too large");
+  b.ntiles = (int)tl.size();
+  b.nodd = (int)odd.size();
+  b.launches = b.ntiles ? launches : 0;
+  b.launches_tb = tltb.empty() ? 0 : launches_tb;
+  hipDeviceProp_t prop;
+  STENCIL_HIP_TRY(hipGetDeviceProperties(&prop, device));
+  b.nblocks = std::max(1, std::min(b.ntiles, prop.multiProcessorCount * 32));
+  hipError_t e = hipMalloc(&b.d_tiles, sizeof(Tile) * std::max<size_t>(1, tl.size()));
+  if (e == hipSuccess) e = hipMalloc(&b.d_tiles_tb, sizeof(Tile) * std::max<size_t>(1, tltb.size()));
+  if (e == hipSuccess && !tltb.empty())
+    e = hipMemcpy(b.d_tiles_tb, tltb.data(), sizeof(Tile) * tltb.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&b.d_grids, sizeof(GridInfo) * gi.size());
+  if (e == hipSuccess) e = hipMalloc(&b.d_w, sizeof(float) * std::max<size_t>(1, wt.size()));
+  if (e == hipSuccess) e = hipMalloc(&b.d_odd, sizeof(int) * std::max<size_t>(1, odd.size()));
+  if (e == hipSuccess && !tl.empty())
+    e = hipMemcpy(b.d_tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b.d_grids, gi.data(), sizeof(GridInfo) * gi.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !wt.empty()) e = hipMemcpy(b.d_w, wt.data(), sizeof(float) * wt.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !odd.empty()) e = hipMemcpy(b.d_odd, odd.data(), sizeof(int) * odd.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && use_graph) {
+    // capture on a private stream, replayed later on the caller's stream
+    e = hipStreamCreateWithFlags(&b.graph_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(b.graph_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t e2 = enqueue(b, b.graph_stream);
+      e = hipStreamEndCapture(b.graph_stream, &b.graph);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0);
+    if (b.graph_stream) (void)hipStreamDestroy(b.graph_stream);
+    b.graph_stream = nullptr;
+  }
+  if (e != hipSuccess) {
+    free_entry(b);
+    return hip_fail(e, "batched setup");
+  }
+  return STENCIL_OK;
+}
+
+// Time m = 1..max_m for one (stencil, size class) on a batch of grids of
+// the class's side, as the batch runs them (fused strips, one-step tiles,
+// copy back), over min(T, 64) original steps; the fastest of three runs per m
+// is compared, and a larger m must win by 3% (ties go to the smaller m).
+// The tuning batch holds about 2^27 points, enough to fill the GPU in every
+// launch: in a real batch a class shares its launches with the other
+// classes, so its cost is its throughput, not the latency of a launch of its
+// grids alone (which would favour fewer, less efficient launches).
+int tune_batched(stencil_plan p, int side, int max_m, int64_t T, hipStream_t stream, int device,
+                 int *best_m) {
+  const int64_t pts = (int64_t)side * side;
+  const int cnt = (int)std::max<int64_t>(1, std::min<int64_t>(1 << 15, ((int64_t)1 << 27) / pts));
+  const size_t bytes = (size_t)cnt * pts * sizeof(float);
+  float *a = nullptr, *b = nullptr;
+  STENCIL_HIP_TRY(hipMalloc(&a, bytes));
+  hipError_t e = hipMalloc(&b, bytes);
+  if (e != hipSuccess) {
+    (void)hipFree(a);
+    return hip_fail(e, "tune alloc");
+  }
+  (void)hipMemsetAsync(a, 0, bytes, stream);
+  std::vector<stencil_grid> gs(cnt);
+  std::vector<stencil_plan> ps(cnt, p);
+  for (int i = 0; i < cnt; ++i) {
+    gs[i] = stencil_grid{};
+    gs[i].data = a + (size_t)i * pts;
+    gs[i].scratch = b + (size_t)i * pts;
+    gs[i].dtype = STENCIL_F32;
+    gs[i].dim = 2;
+    gs[i].shape[0] = gs[i].shape[1] = side;
+    gs[i].stream = stream;
+  }
+  const int64_t Tt = std::min<int64_t>(T, 64);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  double best = 1e30;
+  *best_m = 1;
+  int rc = STENCIL_OK;
+  for (int m = 1; m <= max_m && rc == STENCIL_OK; ++m) {
+    if (m * p->r > kMaxBatchRadius || side < 2 * m * p->r + 1) break;
+    BatchEntry be;
+    rc = build_entry(ps.data(), gs.data(), cnt, Tt, std::vector<int>(cnt, m), false, device, be);
+    if (rc) break;
+    float ms = 1e30f;
+    hipError_t he = enqueue(be, stream);  // warm
+    for (int rep = 0; rep < 3 && he == hipSuccess; ++rep) {
+      (void)hipEventRecord(e0, stream);
+      he = enqueue(be, stream);
+      (void)hipEventRecord(e1, stream);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      ms = std::min(ms, t);
+    }
+    free_entry(be);
+    if (he != hipSuccess) {
+      rc = hip_fail(he, "tune run");
+      break;
+    }
+    if (ms < best * 0.97) {  // 3% margin, ties to smaller m
+      best = ms;
+      *best_m = m;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(stream);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  return rc;
 }
 
 }  // namespace
@@ -545,12 +765,8 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
     if (it != tab.end()) {
       m = it->second;
     } else if (autotune) {
-      // a representative of the class that runs as the batch will: sides of
-      // 256 and more fuse their passes in the batch, so time a vector-aligned
-      // side (which the single-grid sweep fuses too)
-      int rep_side = (int)std::min<int64_t>(side, 1 << 12);
-      if (rep_side >= 256) rep_side = (rep_side + 3) / 4 * 4;
-      int rc = tune_one(p, rep_side, max_m, stream, &m);
+      // this grid's side represents its class
+      int rc = tune_batched(p, (int)std::min<int64_t>(side, 1 << 12), max_m, T, stream, device, &m);
       if (rc) return rc;
       tab[key] = m;
       tuned_any = true;
@@ -564,157 +780,26 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
     for (int i = 0; i < count; ++i) opts->chosen_m[i] = m_of[i];
 
   // --- signature of this batch (pointers, sizes, plans, fold depths, T)
-  std::ostringstream sig;
-  sig << device << ":" << T << ":" << (use_graph ? 1 : 0) << ":" << (uintptr_t)stream;
-  for (int i = 0; i < count; ++i)
-    sig << "|" << (uintptr_t)plans[i] << "," << (uintptr_t)grids[i].data << ","
-        << (uintptr_t)grids[i].scratch << "," << grids[i].shape[0] << "x" << grids[i].shape[1]
-        << "," << m_of[i];
-  const std::string key = sig.str();
+  std::vector<uint64_t> key;
+  key.reserve(4 + 6 * (size_t)count);
+  key.push_back((uint64_t)device);
+  key.push_back((uint64_t)T);
+  key.push_back(use_graph ? 1 : 0);
+  key.push_back((uint64_t)(uintptr_t)stream);
+  for (int i = 0; i < count; ++i) {
+    key.push_back((uint64_t)(uintptr_t)plans[i]);
+    key.push_back((uint64_t)(uintptr_t)grids[i].data);
+    key.push_back((uint64_t)(uintptr_t)grids[i].scratch);
+    key.push_back((uint64_t)grids[i].shape[0]);
+    key.push_back((uint64_t)grids[i].shape[1]);
+    key.push_back((uint64_t)m_of[i]);
+  }
   auto hit = std::find_if(g_cache.begin(), g_cache.end(),
                           [&](const BatchEntry &b) { return b.key == key; });
   if (hit == g_cache.end()) {
     BatchEntry b;
     b.key = key;
-    b.device = device;
-    std::vector<GridInfo> gi(count);
-    std::vector<float> wt;
-    std::map<std::pair<stencil_plan, int>, int> woff;
-    auto weights_at = [&](stencil_plan p, int m, int *off) -> int {
-      auto f = woff.find({p, m});
-      if (f != woff.end()) {
-        *off = f->second;
-        return STENCIL_OK;
-      }
-      const std::vector<float> *w;
-      int rc = plan_weights32(p, m, w);
-      if (rc) return rc;
-      *off = (int)wt.size();
-      wt.insert(wt.end(), w->begin(), w->end());
-      woff[{p, m}] = *off;
-      return STENCIL_OK;
-    };
-    std::vector<std::pair<int64_t, Tile>> tiles, tiles_tb[kTbGroups];
-    std::vector<int> odd;
-    int launches = 0, launches_tb = 0;
-    for (int i = 0; i < count; ++i) {
-      const stencil_plan p = plans[i];
-      const stencil_grid &g = grids[i];
-      const int m = m_of[i];
-      GridInfo &G = gi[i];
-      G.data = (float *)g.data;
-      G.scratch = (float *)g.scratch;
-      G.ny = (int)g.shape[0];
-      G.nx = (int)g.shape[1];
-      G.q = m > 1 ? (int)(T / m) : 0;
-      G.s = m > 1 ? (int)(T % m) : (int)T;
-      const bool vx4 = (G.nx % 4 == 0) && ((uintptr_t)g.data % 16 == 0) &&
-                       ((uintptr_t)g.scratch % 16 == 0);
-      const bool star = p->shape == STENCIL_STAR;
-      G.var_p = variant_id(p->r, star, vx4);
-      G.var_f = variant_id(m * p->r, star, vx4);
-      int rc = weights_at(p, 1, &G.w_p);
-      if (rc) return rc;
-      G.w_f = G.w_p;
-      if (m > 1 && (rc = weights_at(p, m, &G.w_f))) return rc;
-      const int R = m * p->r;
-      // fused passes: the folded applications (the plain ones at m = 1) of
-      // grids of >= 256 vector-aligned columns, up to tb_kmax(R) per pass
-      G.fpass = G.nfull = G.tail = 0;
-      if (G.nx >= 256 && R <= kMaxBatchRadius && G.ny >= 2 * tb_kmax(R) * R + 1) {
-        const int apps = m > 1 ? G.q : G.s;
-        const int rest = m > 1 ? G.s : 0;
-        const int KM = tb_kmax(R);
-        if (apps > 1) {
-          // full passes, then the remainder.  An odd launch count is not
-          // made even by splitting a pass: a pass costs about the same time
-          // whatever its K (it is bound by the strips' memory latency),
-          // more than copying the grid back
-          G.nfull = apps / KM;
-          G.tail = apps % KM;
-          G.fpass = G.nfull + (G.tail > 0);
-          G.q = 0;
-          G.s = rest;
-        }
-      }
-      const int sweeps = G.fpass + (G.fpass ? G.s : G.q + G.s);
-      b.passes.push_back(sweeps);
-      launches = std::max(launches, G.fpass ? G.s : G.q + G.s);
-      launches_tb = std::max(launches_tb, G.fpass);
-      if (sweeps % 2) odd.push_back(i);
-      if (G.fpass) {
-        constexpr int kWout1 = 256 - 2 * tb_border(tb_kmax(1), 1);
-        constexpr int kWout2 = 256 - 2 * tb_border(tb_kmax(2), 2);
-        const int wout = R == 1 ? kWout1 : kWout2;
-        const int kk = G.nfull ? tb_kmax(R) : G.tail;
-        const int rows = tb_rows();
-        for (int y0 = 0; y0 < G.ny; y0 += rows)
-          for (int x0 = 0; x0 < G.nx; x0 += wout) {
-            const int y1 = std::min(G.ny, y0 + rows);
-            const int64_t cost = (int64_t)(y1 - y0 + 2 * kk * R) * kk * (2 * R + 1);
-            tiles_tb[(R - 1) * 2 + (vx4 ? 1 : 0)].push_back({cost, Tile{i, x0, y0, y1}});
-          }
-      }
-      const int bx = 256;
-      const int Rp = G.fpass ? p->r : R;  // one-step work of fused grids is plain
-      if (G.fpass == 0 || G.s > 0)
-        for (int y0 = 0; y0 < G.ny; y0 += kTileRows)
-          for (int x0 = 0; x0 < G.nx; x0 += bx) {
-            const int y1 = std::min(G.ny, y0 + kTileRows);
-            const int64_t cost = (int64_t)(y1 - y0 + 2 * Rp) * (2 * Rp + 1);
-            tiles.push_back({cost, Tile{i, x0, y0, y1}});
-          }
-    }
-    auto by_cost = [](const auto &a, const auto &b) { return a.first > b.first; };
-    std::stable_sort(tiles.begin(), tiles.end(), by_cost);
-    std::vector<Tile> tl(tiles.size()), tltb;
-    for (size_t t = 0; t < tiles.size(); ++t) tl[t] = tiles[t].second;
-    for (int grp = 0; grp < kTbGroups; ++grp) {
-      // strips in grid, row band, column order (neighbours adjacent); every
-      // block is resident at once or nearly, so cost order matters little
-      static const bool by_cost_env = std::getenv("STENCIL_BATCH_TB_SORT") != nullptr;
-      if (by_cost_env) std::stable_sort(tiles_tb[grp].begin(), tiles_tb[grp].end(), by_cost);
-      b.tb_off[grp] = (int)tltb.size();
-      for (const auto &ct : tiles_tb[grp]) tltb.push_back(ct.second);
-    }
-    b.tb_off[kTbGroups] = (int)tltb.size();
-    if (tltb.size() > (size_t)((1LL << 31) - 1)) return fail(STENCIL_E_UNSUPPORTED, "batch too large");
-    b.ntiles = (int)tl.size();
-    b.nodd = (int)odd.size();
-    b.launches = b.ntiles ? launches : 0;
-    b.launches_tb = tltb.empty() ? 0 : launches_tb;
-    hipDeviceProp_t prop;
-    STENCIL_HIP_TRY(hipGetDeviceProperties(&prop, device));
-    b.nblocks = std::max(1, std::min(b.ntiles, prop.multiProcessorCount * 32));
-    hipError_t e = hipMalloc(&b.d_tiles, sizeof(Tile) * std::max<size_t>(1, tl.size()));
-    if (e == hipSuccess) e = hipMalloc(&b.d_tiles_tb, sizeof(Tile) * std::max<size_t>(1, tltb.size()));
-    if (e == hipSuccess && !tltb.empty())
-      e = hipMemcpy(b.d_tiles_tb, tltb.data(), sizeof(Tile) * tltb.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&b.d_grids, sizeof(GridInfo) * gi.size());
-    if (e == hipSuccess) e = hipMalloc(&b.d_w, sizeof(float) * std::max<size_t>(1, wt.size()));
-    if (e == hipSuccess) e = hipMalloc(&b.d_odd, sizeof(int) * std::max<size_t>(1, odd.size()));
-    if (e == hipSuccess && !tl.empty())
-      e = hipMemcpy(b.d_tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b.d_grids, gi.data(), sizeof(GridInfo) * gi.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !wt.empty()) e = hipMemcpy(b.d_w, wt.data(), sizeof(float) * wt.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !odd.empty()) e = hipMemcpy(b.d_odd, odd.data(), sizeof(int) * odd.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess && use_graph) {
-      // capture on a private stream, replayed later on the caller's stream
-      e = hipStreamCreateWithFlags(&b.graph_stream, hipStreamNonBlocking);
-      if (e == hipSuccess) e = hipStreamBeginCapture(b.graph_stream, hipStreamCaptureModeThreadLocal);
-      if (e == hipSuccess) {
-        hipError_t e2 = enqueue(b, b.graph_stream);
-        e = hipStreamEndCapture(b.graph_stream, &b.graph);
-        if (e == hipSuccess) e = e2;
-      }
-      if (e == hipSuccess) e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0);
-      if (b.graph_stream) (void)hipStreamDestroy(b.graph_stream);
-      b.graph_stream = nullptr;
-    }
-    if (e != hipSuccess) {
-      free_entry(b);
-      return hip_fail(e, "batched setup");
-    }
+    if (int rc = build_entry(plans, grids, count, T, m_of, use_graph, device, b)) return rc;
     g_cache.push_front(b);
     if (g_cache.size() > kCacheEntries) {
       free_entry(g_cache.back());

@@ -623,11 +623,10 @@ def test_life_glider_on_gpu():
 
 @pytest.mark.parametrize("T,m", [(50, 1), (21, 2), (3, 1), (13, 1), (15, 2), (2, 1), (16, 1)])
 def test_batched_fused_passes_bit_exact(tmp_path, T, m):
-    """Grids of >= 256 columns run fused passes (full passes of 8 plain
-    applications at radius 1, 4 at radius 2, then one pass of the remainder,
-    e.g. 50 = 6 x 8 + 2), the narrower ones one step per launch, then the
-    plain remainder; odd launch counts end in a copy back.  Every grid
-    bit-exact against the oracle's mirror."""
+    """Fused passes (full passes of 8 plain applications at radius 1, 4 at
+    radius 2, then one pass of the remainder, e.g. 50 = 6 x 8 + 2), then the
+    plain remainder one step per launch; odd launch counts end in a copy
+    back.  Every grid bit-exact against the oracle's mirror."""
     sides = [512, 1024, 260, 300, 64, 256]
     kinds = [synth.STAR, synth.BOX, synth.STAR, synth.BOX, synth.STAR, synth.BOX]
     weights = [synth.WORKLOADS["star2d"].weights, synth.WORKLOADS["box2d"].weights] * 3
@@ -639,6 +638,35 @@ def test_batched_fused_passes_bit_exact(tmp_path, T, m):
     assert chosen == [m] * len(grids)
     for g, w, o in zip(grids, weights, outs):
         assert np.array_equal(o, oracle.folded_reference_f32(w, g, T, m))
+
+
+# (ny, nx) around every strip-layout threshold: 64-column strips from 55
+# columns (radius 1 only), 128-column strips from 119, 256-column strips from
+# 247, remainders covered by narrow strips, too few rows to fuse (16 < 17),
+# radius-2 folds on grids too narrow for their strips (one step per launch)
+NARROW_SHAPES = [(70, 55), (64, 54), (100, 119), (81, 118), (90, 247), (65, 246), (40, 290),
+                 (33, 700), (17, 200), (16, 300), (257, 301), (120, 252), (96, 480), (50, 484)]
+
+
+@pytest.mark.parametrize("T,m", [(50, 1), (21, 2), (13, 1), (15, 2)])
+def test_batched_narrow_strips_bit_exact(tmp_path, T, m):
+    """Fused passes cover a grid's columns with 256-column strips and its
+    last columns (or a whole narrow grid) with 128- and 64-column strips;
+    grids no layout fits run one step per launch.  Every grid bit-exact
+    against the oracle's mirror, stars and boxes, rows of whole vectors or
+    not."""
+    kinds = [synth.STAR if i % 2 == 0 else synth.BOX for i in range(len(NARROW_SHAPES))]
+    weights = [synth.WORKLOADS["star2d"].weights if k == synth.STAR
+               else synth.WORKLOADS["box2d"].weights for k in kinds]
+    grids = [synth.grid_f32(sh, stream=5 + i % 10) for i, sh in enumerate(NARROW_SHAPES)]
+    print("batched narrow strips T", T, "m", m, NARROW_SHAPES, flush=True)
+    cache = tmp_path / "m.txt"
+    cache.write_text("".join("stencil-batched-m %d 1 %d %d\n" % (sh, c, m)
+                             for sh in (0, 1) for c in range(3, 12)))
+    outs, chosen = _run_batched(kinds, weights, grids, T, tune_cache=str(cache), max_m=m)
+    assert chosen == [m] * len(grids)
+    for g, w, o, sh in zip(grids, weights, outs, NARROW_SHAPES):
+        assert np.array_equal(o, oracle.folded_reference_f32(w, g, T, m)), sh
 
 
 GRAPH_CASES = [
