@@ -25,9 +25,11 @@
 #include <list>
 #include <map>
 #include <mutex>
+#include <set>
 #include <sstream>
 #include <string>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -47,10 +49,10 @@ struct GridInfo {
   int q, s;          // folded sweeps first, then plain sweeps
   int var_f, var_p;  // kernel variant of the folded and the plain operator
   int w_f, w_p;      // offsets of their weights in the weight table
-  // Grids of at least 256 columns fuse the folded (or, at
-  // m = 1, the plain) applications: fpass launches of the fused kernel
-  // first, nfull of KMAX applications and then one of the remaining tail
-  // (< KMAX); the one-step launches then run the plain remainder only.
+  // Grids that a strip layout fits fuse the folded (or, at m = 1, the
+  // plain) applications: fpass passes of the fused kernel first, the
+  // applications spread evenly (the first nfull passes run tail + 1, the
+  // others tail); the one-step launches then run the plain remainder only.
   int fpass, nfull, tail;
 };
 
@@ -63,6 +65,11 @@ __host__ __device__ constexpr int variant_id(int R, bool diamond, bool vx4) {
   return (R - 1) * 4 + (diamond ? 2 : 0) + (vx4 ? 1 : 0);
 }
 __host__ __device__ constexpr bool variant_diamond(int var) { return (var & 2) != 0; }
+
+// applications of a fused grid's pass k (k < fpass)
+__host__ __device__ inline int pass_apps(const GridInfo &g, int k) {
+  return k < g.nfull ? g.tail + 1 : g.tail;
+}
 
 // Variants: aligned rows of >= 256 floats use vector lanes (two rows of
 // look-ahead), the rest strided lanes (4 coalesced scalars per lane).
@@ -118,14 +125,13 @@ k_batched(const Tile *__restrict__ tiles, int ntiles, const GridInfo *__restrict
 // The fused 2D strip (several applications of one operator per pass, one
 // wavefront per 256-column strip streaming down y, each application a
 // pipeline stage with its own accumulator queue, neighbour columns by DPP;
-// the single-grid form is described with the fused 2D sweep) with the number
-// of applications K <= KMAX.  Full passes compile K = KMAX.  A grid's
-// last, shorter pass runs all KMAX stages as well and stores stage K-1's
-// output, picked by a select: a branch per stage would make the compiler
-// drain every outstanding load where the branches merge, and a body per K
-// makes the kernel about twice as large, which measured 10% slower on a
-// mixed batch.  Strips keep the KMAX border, so one tiling serves every K.  Canonical order, bit-identical to K single
-// applications.
+// the single-grid form is described with the fused 2D sweep) with KC <= KMAX
+// applications, a compile-time count: each pass launches the kernel of every
+// KC its grids take in that pass (blocks of other grids return at once), so
+// a short pass costs its own stages only (a runtime count would make the
+// compiler drain every outstanding load where stage branches merge).
+// Strips keep the KMAX border, so one tiling serves every KC.  Canonical
+// order, bit-identical to KC single applications.
 
 static int tb_rows() {
   static const int rows = [] {
@@ -155,9 +161,9 @@ __host__ __device__ constexpr int tb_kmax(int R) { return R == 1 ? 8 : 4; }
 // on its own, and stores column by column.  The strip's columns must span
 // less than twice the grid's width (each column wraps at most once):
 // 64 * VX - B - 2 < nx.
-template <int R, int MASK, int VX, bool VEC, bool FULL>
+template <int R, int MASK, int VX, bool VEC, int K>
 __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, int ny, int nx,
-                         int xo0, int y0, int y1, int Kr, const float *__restrict__ wt) {
+                         int xo0, int y0, int y1, const float *__restrict__ wt) {
   static_assert(VX >= R && (!VEC || VX == 4), "strip layout");
   using k2d::fmat;
   using k2d::in_mask;
@@ -169,7 +175,7 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
   constexpr int KMAX = tb_kmax(R);
   constexpr int B = tb_border(KMAX, R);
   constexpr int WOUT = 64 * VX - 2 * B;
-  const int K = FULL ? KMAX : Kr;
+  static_assert(K >= 1 && K <= KMAX, "stages per pass");
   float W[S * S];
 #pragma unroll
   for (int i = 0; i < S * S; ++i) W[i] = wt[i];
@@ -184,19 +190,19 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
 #pragma unroll
   for (int v = 0; v < VX; ++v) store_v[v] = lo + v >= 0 && lo + v < WOUT && xo0 + lo + v < nx;
   const int jstart = y0 - K * R, jend = y1 + K * R;
-  float acc[KMAX][NU][VX];
+  float acc[K][NU][VX];
 #pragma unroll
-  for (int st = 0; st < KMAX; ++st)
+  for (int st = 0; st < K; ++st)
 #pragma unroll
     for (int k = 0; k < NU; ++k)
 #pragma unroll
       for (int v = 0; v < VX; ++v) acc[st][k][v] = 0.0f;
   auto row = [&](const int j, const int u, const float (&in_row)[VX]) {
-    float cur[VX], res[VX];
+    float cur[VX];
 #pragma unroll
-    for (int v = 0; v < VX; ++v) cur[v] = res[v] = in_row[v];
+    for (int v = 0; v < VX; ++v) cur[v] = in_row[v];
 #pragma unroll
-    for (int st = 0; st < KMAX; ++st) {
+    for (int st = 0; st < K; ++st) {
       {
         float win[VX + 2 * R];
 #pragma unroll
@@ -222,16 +228,12 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
         }
 #pragma unroll
         for (int v = 0; v < VX; ++v) cur[v] = acc[st][u % NU][v];
-        if constexpr (!FULL) {
-#pragma unroll
-          for (int v = 0; v < VX; ++v) res[v] = st == K - 1 ? cur[v] : res[v];
-        }
       }
     }
     const int yd = j - K * R;
     if (yd >= y0 && yd < y1) {
       float *dst = out + (size_t)yd * nx + xo0 + lo;
-      const float(&val)[VX] = FULL ? cur : res;
+      const float(&val)[VX] = cur;
       if constexpr (VEC) {
         if (store_ok) store_vec<float, 4>(dst, val);
       } else {
@@ -265,11 +267,11 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
   }
 }
 
-// One fused pass of every fused grid that has pass k: one block per strip.
-// One kernel per radius and row layout, so that each gets its own register
-// allocation (a kernel holding every variant would run all of them at the
-// occupancy of the largest).
-template <int R, int VX, bool VEC>
+// Pass k of every fused grid whose pass k has KC applications: one block per
+// strip.  One kernel per radius, row layout and KC, so that each gets its own
+// register allocation (a kernel holding every variant would run all of them
+// at the occupancy of the largest).
+template <int R, int VX, bool VEC, int KC>
 __global__ void __launch_bounds__(64)
 k_batched_tb(const Tile *__restrict__ tiles, const GridInfo *__restrict__ grids,
              const float *__restrict__ wtab, int k) {
@@ -280,20 +282,14 @@ k_batched_tb(const Tile *__restrict__ tiles, const GridInfo *__restrict__ grids,
   const int x = bi & 7, q = nb >> 3, r = nb & 7;
   const Tile tl = tiles[x * q + min(x, r) + (bi >> 3)];
   const GridInfo g = grids[tl.grid];
-  if (k >= g.fpass) return;
-  constexpr int KMAX = tb_kmax(R);
-  const int K = k < g.nfull ? KMAX : g.tail;
+  if (k >= g.fpass || pass_apps(g, k) != KC) return;
   const float *in = (k & 1) ? g.scratch : g.data;
   float *out = (k & 1) ? g.data : g.scratch;
   const float *w = wtab + g.w_f;
-  const bool dia = variant_diamond(g.var_f);
-  if (K == KMAX) {
-    if (dia) tb_strip<R, MASK_DIAMOND, VX, VEC, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
-    else tb_strip<R, MASK_BOX, VX, VEC, true>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
-  } else {
-    if (dia) tb_strip<R, MASK_DIAMOND, VX, VEC, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
-    else tb_strip<R, MASK_BOX, VX, VEC, false>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, K, w);
-  }
+  if (variant_diamond(g.var_f))
+    tb_strip<R, MASK_DIAMOND, VX, VEC, KC>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w);
+  else
+    tb_strip<R, MASK_BOX, VX, VEC, KC>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w);
 }
 
 // Strip layouts of the fused passes, and their tile groups: group =
@@ -423,7 +419,7 @@ struct BatchEntry {
   int device = 0;
   Tile *d_tiles_tb = nullptr;  // fused strips (one block each), by group
   int tb_off[kTbGroups + 1] = {};
-  int launches_tb = 0;
+  std::vector<std::tuple<int, int, int>> tb_launch;  // (pass, group, applications)
   Tile *d_tiles = nullptr;
   GridInfo *d_grids = nullptr;
   float *d_w = nullptr;
@@ -453,26 +449,42 @@ void free_entry(BatchEntry &b) {
   (void)hipSetDevice(cur);
 }
 
+// The fused-pass kernel of a tile group for KC applications per pass.
+template <int R, int VX, bool VEC, int... Ks>
+const void *tb_kernel_kc(int kc, std::integer_sequence<int, Ks...>) {
+  const void *f = nullptr;
+  ((kc == Ks + 1 ? (f = reinterpret_cast<const void *>(&k_batched_tb<R, VX, VEC, Ks + 1>)) : f), ...);
+  return f;
+}
+const void *tb_kernel(int grp, int kc) {
+  using K1 = std::make_integer_sequence<int, tb_kmax(1)>;
+  using K2 = std::make_integer_sequence<int, tb_kmax(2)>;
+  switch (grp) {
+    case kTb4: return tb_kernel_kc<1, 4, false>(kc, K1());
+    case kTb4Vec: return tb_kernel_kc<1, 4, true>(kc, K1());
+    case kTb2: return tb_kernel_kc<1, 2, false>(kc, K1());
+    case kTb1: return tb_kernel_kc<1, 1, false>(kc, K1());
+    case kTbLayouts + kTb4: return tb_kernel_kc<2, 4, false>(kc, K2());
+    case kTbLayouts + kTb4Vec: return tb_kernel_kc<2, 4, true>(kc, K2());
+    case kTbLayouts + kTb2: return tb_kernel_kc<2, 2, false>(kc, K2());
+    default: return nullptr;  // no one-column strips at radius 2
+  }
+}
+
 hipError_t enqueue(const BatchEntry &b, hipStream_t s) {
-  for (int k = 0; k < b.launches_tb; ++k) {
-    for (int grp = 0; grp < kTbGroups; ++grp) {
-      const int n = b.tb_off[grp + 1] - b.tb_off[grp];
-      if (n == 0) continue;
-      const Tile *t = b.d_tiles_tb + b.tb_off[grp];
-      const dim3 gr(n), bl(64);
-      switch (grp) {
-        case kTb4: hipLaunchKernelGGL((k_batched_tb<1, 4, false>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
-        case kTb4Vec: hipLaunchKernelGGL((k_batched_tb<1, 4, true>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
-        case kTb2: hipLaunchKernelGGL((k_batched_tb<1, 2, false>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
-        case kTb1: hipLaunchKernelGGL((k_batched_tb<1, 1, false>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
-        case kTbLayouts + kTb4: hipLaunchKernelGGL((k_batched_tb<2, 4, false>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
-        case kTbLayouts + kTb4Vec: hipLaunchKernelGGL((k_batched_tb<2, 4, true>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
-        case kTbLayouts + kTb2: hipLaunchKernelGGL((k_batched_tb<2, 2, false>), gr, bl, 0, s, t, b.d_grids, b.d_w, k); break;
-        default: return hipErrorInvalidValue;  // no one-column strips at radius 2
-      }
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
+  for (const auto &l : b.tb_launch) {
+    int k = std::get<0>(l);
+    const int grp = std::get<1>(l), kc = std::get<2>(l);
+    const int n = b.tb_off[grp + 1] - b.tb_off[grp];
+    const void *f = tb_kernel(grp, kc);
+    if (n == 0 || !f) return hipErrorInvalidValue;
+    const Tile *t = b.d_tiles_tb + b.tb_off[grp];
+    const GridInfo *g = b.d_grids;
+    const float *w = b.d_w;
+    void *args[] = {&t, &g, &w, &k};
+    hipError_t e = hipLaunchKernel(f, dim3(n), dim3(64), args, 0, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
   for (int k = 0; k < b.launches; ++k) {
     hipLaunchKernelGGL(k_batched, dim3(b.nblocks), dim3(64), 0, s, b.d_tiles, b.ntiles,
@@ -513,8 +525,9 @@ int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count,
     return STENCIL_OK;
   };
   std::vector<std::pair<int64_t, Tile>> tiles, tiles_tb[kTbGroups];
+  std::set<std::tuple<int, int, int>> tb_need;  // (pass, group, applications)
   std::vector<int> odd;
-  int launches = 0, launches_tb = 0;
+  int launches = 0;
   for (int i = 0; i < count; ++i) {
     const stencil_plan p = plans[i];
     const stencil_grid &g = grids[i];
@@ -547,13 +560,13 @@ int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count,
       const int rest = m > 1 ? G.s : 0;
       const int KM = tb_kmax(R);
       if (apps > 1) {
-        // full passes, then the remainder.  An odd launch count is not
-        // made even by splitting a pass: a pass costs about the same time
-        // whatever its K (it is bound by the strips' memory latency),
-        // more than copying the grid back
-        G.nfull = apps / KM;
-        G.tail = apps % KM;
-        G.fpass = G.nfull + (G.tail > 0);
+        // the fewest passes, applications spread evenly (pass k takes
+        // tail + 1 while k < nfull, else tail).  An odd launch count is not
+        // made even by one more pass: a pass costs more than copying the
+        // grid back
+        G.fpass = (apps + KM - 1) / KM;
+        G.tail = apps / G.fpass;
+        G.nfull = apps % G.fpass;
         G.q = 0;
         G.s = rest;
       }
@@ -561,10 +574,9 @@ int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count,
     const int sweeps = G.fpass + (G.fpass ? G.s : G.q + G.s);
     b.passes.push_back(sweeps);
     launches = std::max(launches, G.fpass ? G.s : G.q + G.s);
-    launches_tb = std::max(launches_tb, G.fpass);
     if (sweeps % 2) odd.push_back(i);
     if (G.fpass) {
-      const int kk = G.nfull ? tb_kmax(R) : G.tail;
+      const int kk = pass_apps(G, 0);
       const int rows = tb_rows();
       for (int y0 = 0; y0 < G.ny; y0 += rows)
         for (const auto &st : strips) {
@@ -572,6 +584,10 @@ int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count,
           const int64_t cost = (int64_t)(y1 - y0 + 2 * kk * R) * kk * (2 * R + 1) * tb_vx(st.first);
           tiles_tb[(R - 1) * kTbLayouts + st.first].push_back({cost, Tile{i, st.second, y0, y1}});
         }
+      // the kernels pass k launches: (group, applications) of this grid
+      for (const auto &st : strips)
+        for (int k = 0; k < G.fpass; ++k)
+          tb_need.insert({k, (R - 1) * kTbLayouts + st.first, pass_apps(G, k)});
     }
     const int bx = 256;
     const int Rp = G.fpass ? p->r : R;  // one-step work of fused grids is plain
@@ -600,7 +616,7 @@ int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count,
   b.ntiles = (int)tl.size();
   b.nodd = (int)odd.size();
   b.launches = b.ntiles ? launches : 0;
-  b.launches_tb = tltb.empty() ? 0 : launches_tb;
+  b.tb_launch.assign(tb_need.begin(), tb_need.end());
   hipDeviceProp_t prop;
   STENCIL_HIP_TRY(hipGetDeviceProperties(&prop, device));
   b.nblocks = std::max(1, std::min(b.ntiles, prop.multiProcessorCount * 32));
