@@ -311,10 +311,20 @@ __host__ __device__ constexpr int tb_min_nx(int R, int layout) {
 // Grids whose total sweep count is odd end in scratch: copy them back.
 __global__ void __launch_bounds__(256)
 k_batched_copyback(const GridInfo *__restrict__ grids, const int *__restrict__ odd, int nodd) {
+  using V = __attribute__((ext_vector_type(4))) float;
   for (int i = blockIdx.y; i < nodd; i += gridDim.y) {
     const GridInfo g = grids[odd[i]];
     const int64_t n = (int64_t)g.nx * g.ny;
-    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t head = 0;  // 16-byte vectors where both buffers allow them
+    if ((((uintptr_t)g.data | (uintptr_t)g.scratch) & 15) == 0) {
+      head = n / 4 * 4;
+      const V *src = reinterpret_cast<const V *>(g.scratch);
+      V *dst = reinterpret_cast<V *>(g.data);
+      for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n / 4; e += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + e), dst + e);
+    }
+    for (int64_t e = head + blockIdx.x * 256 + threadIdx.x; e < n; e += stride)
       g.data[e] = g.scratch[e];
   }
 }
