@@ -219,7 +219,8 @@ template <>
 hipError_t launch_k<1, MASK_DIAMOND>(const SweepLaunch &L) {
   switch (L.steps) { TB_CASE(1, MASK_DIAMOND, 2) TB_CASE(1, MASK_DIAMOND, 3) TB_CASE(1, MASK_DIAMOND, 4)
     TB_CASE(1, MASK_DIAMOND, 5) TB_CASE(1, MASK_DIAMOND, 6) TB_CASE(1, MASK_DIAMOND, 7)
-    TB_CASE(1, MASK_DIAMOND, 8) }
+    TB_CASE(1, MASK_DIAMOND, 8) TB_CASE(1, MASK_DIAMOND, 9) TB_CASE(1, MASK_DIAMOND, 10)
+    TB_CASE(1, MASK_DIAMOND, 11) TB_CASE(1, MASK_DIAMOND, 12) }
   return hipErrorNotSupported;
 }
 template <>
@@ -250,6 +251,11 @@ hipError_t launch_k<4, MASK_DIAMOND>(const SweepLaunch &L) {
 // one step per pass already, and fusing only adds the redundant border work.
 int tb_max(int R, int mask) {
   if (mask == MASK_BOX && R >= 3) return 1;
+  static const int star1 = [] {
+    const char *e = std::getenv("STENCIL_TB_STAR_K");
+    return e ? std::max(2, std::min(12, std::atoi(e))) : 12;
+  }();
+  if (R == 1 && mask != MASK_BOX) return star1;
   return R == 1 ? 8 : R == 2 ? 4 : R <= 4 ? 2 : 1;
 }
 

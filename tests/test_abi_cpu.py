@@ -173,11 +173,16 @@ def test_run_schedule_counts_launches():
     applications, fused up to the kernel's depth, an even launch count
     whenever a fusing pass can split once more, else a final copy."""
     star = sf.Plan(synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR)
-    # 2D FP32 radius 1: up to 8 steps per launch; 1000 steps -> 125 -> 126
+    # 2D FP32 radius-1 star: up to 12 steps per launch; 1000 steps -> 84
     s = _sched(star, (8192, 8192), 1000)
+    assert (s["plain_apps"], s["plain_launches"], s["final_copy"]) == (1000, 84, False)
+    # radius-1 box: up to 8; 1000 steps -> 125 -> 126 (even)
+    box = sf.Plan(synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX)
+    s = _sched(box, (8192, 8192), 1000)
     assert (s["plain_apps"], s["plain_launches"], s["final_copy"]) == (1000, 126, False)
     # T = 8 would be one launch: split in two so no copy is needed
     assert _sched(star, (8192, 8192), 8)["plain_launches"] == 2
+    assert _sched(star, (8192, 8192), 12)["plain_launches"] == 2
     # T = 1 cannot split: one launch and a copy
     s = _sched(star, (8192, 8192), 1)
     assert (s["plain_launches"], s["final_copy"]) == (1, True)

@@ -367,7 +367,12 @@ TB_CASES = [
     # (name, weights, kind, shape, T, m, fusion): each launch fuses up to
     # `fusion` steps (0 = library choice); shapes span several 256-column
     # strips with a ragged last strip, and the minimum row count 2KR+1
-    ("star_r1_k8", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (200, 1000), 16, 1, 0),
+    ("star_r1_k8", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (200, 1000), 16, 1, 8),
+    ("star_r1_k12", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (200, 1000), 24, 1, 0),
+    ("star_r1_k10_k11", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (90, 1284), 42, 1, 11),
+    ("star_r1_k9_k10", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (64, 772), 38, 1, 10),
+    ("star_r1_k12_min_rows", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (25, 512), 24, 1,
+     0),
     ("star_r1_min_rows", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (17, 256), 8, 1, 8),
     ("box_r1_k7", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (150, 772), 14, 1, 7),
     ("box_r1_k5_k6", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (99, 516), 11, 1, 6),
