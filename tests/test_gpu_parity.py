@@ -62,6 +62,9 @@ CASES_3D = [
     ("box3d", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (19, 40, 64), 4, 1),
     ("box3d_m2", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (17, 36, 128), 5, 2),
     ("box3d_min_m2", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (5, 5, 5), 4, 2),
+    # two rows per lane (radius-1 box): ragged 32-row and 64-column tiles
+    ("box3d_ragged_tiles", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (7, 45, 130), 3, 1),
+    ("box3d_one_row_tile", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (6, 3, 70), 3, 1),
 ]
 
 CASES_1D = [
