@@ -260,8 +260,11 @@ hipError_t launch_one(const SweepLaunch &L, const std::vector<T> &w) {
   if (const char *e = std::getenv("STENCIL_TILE_Z")) bz = std::atoi(e);
   if (bz <= 0) {
     const int64_t xy = (int64_t)tiles_x * tiles_y;
-    // about 1024 workgroups (128-plane segments at 512^3) measured best
-    const int64_t target_z = std::max<int64_t>(1, (1024 + xy - 1) / xy);
+    // about 1024 workgroups measured best (128-plane segments at 512^3 with
+    // one row per lane), but 512 for two-row tiles at radius 2 (128-plane
+    // segments again: a shorter segment repeats more of its 2R-plane halo)
+    const int64_t wgs = (RY == 2 && R == 2) ? 512 : 1024;
+    const int64_t target_z = std::max<int64_t>(1, (wgs + xy - 1) / xy);
     bz = (int)((nz + target_z - 1) / target_z);
   }
   bz = std::max(bz, std::max(4, 4 * R));
@@ -278,11 +281,10 @@ hipError_t launch_one(const SweepLaunch &L, const std::vector<T> &w) {
   return hipGetLastError();
 }
 
-// Two rows per lane for the FP32 radius-1 box (each slab row read serves
-// both: 4 row reads per 8 outputs instead of 3 per 4, +7% at 512^3); the
-// other operators measured faster with one row (their two-row tiles halve
-// the workgroups per z-segment or cost registers), and STENCIL_3D_RY = 1 or 2
-// forces either for FP32 radius 1-2.
+// Two rows per lane for the FP32 radius-1 box and radius-2 diamond (each
+// slab row read serves both rows: for the box 4 row reads per 8 outputs
+// instead of 3 per 4; +7% and +3% at 512^3); the 7-point star measured faster
+// with one row, and STENCIL_3D_RY = 1 or 2 forces either for FP32 radius 1-2.
 template <typename T, int R, int MASK>
 hipError_t launch_m(const SweepLaunch &L, const std::vector<T> &w) {
   static const int env = [] {
@@ -290,7 +292,8 @@ hipError_t launch_m(const SweepLaunch &L, const std::vector<T> &w) {
     return e ? std::atoi(e) : 0;
   }();
   if constexpr (sizeof(T) == 4 && R <= 2) {
-    const bool two = env == 2 || (env != 1 && MASK == MASK_BOX && R == 1);
+    const bool two = env == 2 || (env != 1 && ((MASK == MASK_BOX && R == 1) ||
+                                              (MASK == MASK_DIAMOND && R == 2)));
     if (two) return launch_one<T, R, MASK, 2>(L, w);
   }
   return launch_one<T, R, MASK, 1>(L, w);
