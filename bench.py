@@ -150,13 +150,26 @@ def cpu_baseline(w, shape_full, dtype, T_full, budget_s, boundary="periodic"):
     shape = tuple(shape_full)
     u0 = synth.grid_f64(shape)
     oracle.sweep(w, u0, 1, boundary)  # warm: threads, page faults
+    # per-step cost from two calls (each call also pays a fixed cost for its
+    # FP64 copies of the grid)
     t0 = time.perf_counter()
     oracle.sweep(w, u0, 2, boundary)
-    per_step = max((time.perf_counter() - t0) / 2, 1e-6)
-    T = int(max(1, min(T_full, budget_s / per_step)))
+    t2 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.sweep(w, u0, 6, boundary)
+    t6 = time.perf_counter() - t0
+    per_step = max((t6 - t2) / 4, t6 / 12, 1e-6)
+    fixed = max(0.0, t2 - 2 * per_step)
+    T = int(max(1, min(T_full, (budget_s - fixed) / per_step)))
     t0 = time.perf_counter()
     oracle.sweep(w, u0, T, boundary)
     dt = time.perf_counter() - t0
+    if dt < 0.7 * budget_s and T < T_full:
+        # short runs overstate the per-step cost: size the timed sample again
+        T = int(max(1, min(T_full, T * budget_s / max(dt, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.sweep(w, u0, T, boundary)
+        dt = time.perf_counter() - t0
     n = int(np.prod(shape))
     return {
         "value": round(n * T / dt / 1e9, 4),
