@@ -283,15 +283,23 @@ int stencil_run_schedule(stencil_plan p, const stencil_grid *g, int64_t T,
                          int64_t *out, int *final_copy);
 
 /*
- * stencil_run_batched -- advance count independent 2D grids by T steps each,
- * grids[i] with plans[i] (plans may repeat; every plan must be 2D), with one
- * persistent launch per (folded) sweep over all grids together and, when
- * opts->use_graph, the whole time loop captured in one hipGraph on
- * grids[0].stream (all grids must name the same stream).  Every grid needs a
- * caller scratch buffer.  The fold depth of each plan is chosen per
- * (stencil, size class) by timing candidates when opts->autotune (largest
- * opts->max_m), else taken from the cache or set to 1; the plans' own fold
- * depth is not changed.  opts may be NULL (no tuning, no graph, m = 1).
+ * stencil_run_batched -- advance count independent 2D grids by T steps each
+ * (Section 1's time loop per grid), grids[i] with plans[i] (plans may repeat;
+ * every plan must be 2D, periodic, radius <= 2; grids FP32).  Grids that a
+ * fused strip fits (at least 17 rows and 55 columns at radius 1, 119 at
+ * radius 2) run their applications several per pass (up to 8 at radius 1, 4
+ * at radius 2; Section 3.4's steps kept on chip), the others one persistent
+ * launch per sweep over all of them together; grids whose pass count is odd
+ * are copied back into data.  With opts->use_graph the whole time loop is
+ * captured once in one hipGraph and replayed on grids[0].stream (all grids
+ * must name the same stream).  Every grid needs a caller scratch buffer.
+ * The fold depth of each plan is chosen per (stencil, radius, size class) by
+ * timing m = 1..opts->max_m on a batch of that class run by these kernels
+ * when opts->autotune, else taken from the cache or set to 1; the plans' own
+ * fold depth is not changed.  Results equal the plain canonical-order sweep
+ * of the chosen operators bit for bit.  opts may be NULL (no tuning, no
+ * graph, m = 1).  The library keeps device tables (and the graph) of the last
+ * four batches, keyed by every argument.
  * Errors: E_ARG, E_UNSUPPORTED, E_NOMEM, E_DEVICE.
  */
 int stencil_run_batched(const stencil_plan *plans, stencil_grid *grids,
