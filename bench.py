@@ -514,6 +514,13 @@ def bench_batched(args):
     roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
     roof["alu_frac"] = round(tfl / FP32_FMA_TFLOPS, 4)
     roof["passes_per_grid_mean"] = round(sum(passes) / len(passes), 3)
+    # the tuned strip heights per (stencil, radius, size class), from the cache
+    heights = {}
+    if os.path.exists(cache):
+        for line in open(cache):
+            f = line.split()
+            if len(f) == 5 and f[0] == "stencil-batched-rows":
+                heights["%s_r%s_class%s" % ("star" if f[1] == "0" else "box", f[2], f[3])] = int(f[4])
     res = {
         "metric": METRIC,
         "value": forms["persistent_graph_tuned"]["gstencil_s"],
@@ -525,7 +532,8 @@ def bench_batched(args):
         "config": {"workload": "batched: 4096 periodic 2D grids, sides log-uniform in [64, 1024], "
                                "5-point star or 9-point box (random positive weights), FP32, T=50",
                    "points": npts, "T": T,
-                   "fold_m_histogram": {str(m): int(sum(1 for x in ms if x == m)) for m in sorted(set(ms))}},
+                   "fold_m_histogram": {str(m): int(sum(1 for x in ms if x == m)) for m in sorted(set(ms))},
+                   "tuned_strip_rows_other_than_64": heights},
         "roofline": roof,
         "forms": forms,
         "taps": {"%s_m%d" % ("star" if k == synth.STAR else "box", m): t

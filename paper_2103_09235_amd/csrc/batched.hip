@@ -133,13 +133,16 @@ k_batched(const Tile *__restrict__ tiles, int ntiles, const GridInfo *__restrict
 // Strips keep the KMAX border, so one tiling serves every KC.  Canonical
 // order, bit-identical to KC single applications.
 
-static int tb_rows() {
+// Strip height (rows a fused strip stores): the default, or the
+// STENCIL_BATCH_TB_ROWS override, which also fixes it for the tuner.
+static int tb_rows_env() {
   static const int rows = [] {
     const char *e = std::getenv("STENCIL_BATCH_TB_ROWS");
-    return e ? std::max(16, std::atoi(e)) : 64;
+    return e ? std::max(16, std::atoi(e)) : 0;
   }();
   return rows;
 }
+static int tb_rows() { return tb_rows_env() ? tb_rows_env() : 64; }
 
 __device__ __forceinline__ float tb_from_left(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
@@ -387,24 +390,37 @@ struct TuneKey {
   }
 };
 
-std::mutex g_mu;
-std::map<std::string, std::map<TuneKey, int>> g_tune;  // per cache file ("" = memory only)
+// A class's tuned choice: fold depth and fused-strip height (0 = default).
+struct TuneVal {
+  int m = 1, rows = 0;
+};
 
-void load_tune_file(const std::string &path, std::map<TuneKey, int> &out) {
+std::mutex g_mu;
+std::map<std::string, std::map<TuneKey, TuneVal>> g_tune;  // per cache file ("" = memory only)
+
+// Cache file lines: "stencil-batched-m shape r cls m" and, optionally,
+// "stencil-batched-rows shape r cls rows".
+void load_tune_file(const std::string &path, std::map<TuneKey, TuneVal> &out) {
   if (path.empty()) return;
   std::ifstream f(path);
   std::string tag;
-  int shape, r, cls, m;
-  while (f >> tag >> shape >> r >> cls >> m)
-    if (tag == "stencil-batched-m") out[TuneKey{shape, r, cls}] = m;
+  int shape, r, cls, v;
+  while (f >> tag >> shape >> r >> cls >> v) {
+    if (tag == "stencil-batched-m") out[TuneKey{shape, r, cls}].m = v;
+    if (tag == "stencil-batched-rows") out[TuneKey{shape, r, cls}].rows = std::max(0, v);
+  }
 }
 
-void save_tune_file(const std::string &path, const std::map<TuneKey, int> &tab) {
+void save_tune_file(const std::string &path, const std::map<TuneKey, TuneVal> &tab) {
   if (path.empty()) return;
   std::ofstream f(path, std::ios::trunc);
-  for (const auto &kv : tab)
-    f << "stencil-batched-m " << kv.first.shape << " " << kv.first.r << " " << kv.first.cls
-      << " " << kv.second << "\n";
+  for (const auto &kv : tab) {
+    const TuneKey &k = kv.first;
+    f << "stencil-batched-m " << k.shape << " " << k.r << " " << k.cls << " " << kv.second.m << "\n";
+    if (kv.second.rows)
+      f << "stencil-batched-rows " << k.shape << " " << k.r << " " << k.cls << " " << kv.second.rows
+        << "\n";
+  }
 }
 
 // Folded FP32 weights of a plan at depth m (cached in the plan).
@@ -515,7 +531,8 @@ hipError_t enqueue(const BatchEntry &b, hipStream_t s) {
 // Builds a batch: fold weights, fused strips and one-step tiles per grid,
 // device tables, and (use_graph) the captured time loop.
 int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count, int64_t T,
-                const std::vector<int> &m_of, bool use_graph, int device, BatchEntry &b) {
+                const std::vector<int> &m_of, const std::vector<int> &rows_of, bool use_graph,
+                int device, BatchEntry &b) {
   b.device = device;
   std::vector<GridInfo> gi(count);
   std::vector<float> wt;
@@ -587,7 +604,7 @@ int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count,
     if (sweeps % 2) odd.push_back(i);
     if (G.fpass) {
       const int kk = pass_apps(G, 0);
-      const int rows = tb_rows();
+      const int rows = rows_of[i] > 0 ? rows_of[i] : tb_rows();
       for (int y0 = 0; y0 < G.ny; y0 += rows)
         for (const auto &st : strips) {
           const int y1 = std::min(G.ny, y0 + rows);
@@ -663,15 +680,18 @@ int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count,
 }
 
 // Time m = 1..max_m for one (stencil, size class) on a batch of grids of
-// the class's side, as the batch runs them (fused strips, one-step tiles,
-// copy back), over min(T, 64) original steps; the fastest of three runs per m
-// is compared, and a larger m must win by 3% (ties go to the smaller m).
+// the class's side, as the batch runs them (fused strips of the default
+// height, one-step tiles, copy back), over min(T, 64) original steps; the
+// fastest of three runs per m is compared, and a larger m must win by 3%
+// (ties go to the smaller m).  The strip height is not tuned: choices that
+// win for a class alone (a larger m, other heights) measured 8% slower on a
+// mixed batch, whose launches they split; a cache line may still pin one.
 // The tuning batch holds about 2^27 points, enough to fill the GPU in every
 // launch: in a real batch a class shares its launches with the other
 // classes, so its cost is its throughput, not the latency of a launch of its
 // grids alone (which would favour fewer, less efficient launches).
 int tune_batched(stencil_plan p, int side, int max_m, int64_t T, hipStream_t stream, int device,
-                 int *best_m) {
+                 TuneVal *best_v) {
   const int64_t pts = (int64_t)side * side;
   const int cnt = (int)std::max<int64_t>(1, std::min<int64_t>(1 << 15, ((int64_t)1 << 27) / pts));
   const size_t bytes = (size_t)cnt * pts * sizeof(float);
@@ -699,12 +719,14 @@ int tune_batched(stencil_plan p, int side, int max_m, int64_t T, hipStream_t str
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   double best = 1e30;
-  *best_m = 1;
+  *best_v = TuneVal();
   int rc = STENCIL_OK;
   for (int m = 1; m <= max_m && rc == STENCIL_OK; ++m) {
+    const int rows = 0;  // the default height
     if (m * p->r > kMaxBatchRadius || side < 2 * m * p->r + 1) break;
     BatchEntry be;
-    rc = build_entry(ps.data(), gs.data(), cnt, Tt, std::vector<int>(cnt, m), false, device, be);
+    rc = build_entry(ps.data(), gs.data(), cnt, Tt, std::vector<int>(cnt, m),
+                     std::vector<int>(cnt, rows), false, device, be);
     if (rc) break;
     float ms = 1e30f;
     hipError_t he = enqueue(be, stream);  // warm
@@ -724,7 +746,7 @@ int tune_batched(stencil_plan p, int side, int max_m, int64_t T, hipStream_t str
     }
     if (ms < best * 0.97) {  // 3% margin, ties to smaller m
       best = ms;
-      *best_m = m;
+      best_v->m = m;
     }
   }
   (void)hipEventDestroy(e0);
@@ -777,29 +799,31 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
   STENCIL_HIP_TRY(hipGetDevice(&device));
   std::lock_guard<std::mutex> lock(g_mu);
 
-  // --- fold depth per grid: tuned per (shape, r, size class), cached
-  std::map<TuneKey, int> &tab = g_tune[cache_path];
+  // --- fold depth and strip height per grid: tuned per (shape, r, size
+  // class), cached
+  std::map<TuneKey, TuneVal> &tab = g_tune[cache_path];
   if (tab.empty()) load_tune_file(cache_path, tab);
-  std::vector<int> m_of(count, 1);
+  std::vector<int> m_of(count, 1), rows_of(count, 0);
   bool tuned_any = false;
   for (int i = 0; i < count; ++i) {
     const stencil_plan p = plans[i];
     const int64_t side = std::min(grids[i].shape[0], grids[i].shape[1]);
     const TuneKey key{p->shape, p->r, size_class(side)};
-    int m = 1;
+    TuneVal v;
     auto it = tab.find(key);
     if (it != tab.end()) {
-      m = it->second;
+      v = it->second;
     } else if (autotune) {
       // this grid's side represents its class
-      int rc = tune_batched(p, (int)std::min<int64_t>(side, 1 << 12), max_m, T, stream, device, &m);
+      int rc = tune_batched(p, (int)std::min<int64_t>(side, 1 << 12), max_m, T, stream, device, &v);
       if (rc) return rc;
-      tab[key] = m;
+      tab[key] = v;
       tuned_any = true;
     }
-    m = std::max(1, std::min(m, max_m));
+    int m = std::max(1, std::min(v.m, max_m));
     while (m > 1 && (m * p->r > kMaxBatchRadius || 2 * m * p->r + 1 > side)) --m;
     m_of[i] = m;
+    rows_of[i] = tb_rows_env() ? 0 : std::max(0, std::min(v.rows, 1 << 16));
   }
   if (tuned_any) save_tune_file(cache_path, tab);
   if (opts && opts->chosen_m)
@@ -807,7 +831,7 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
 
   // --- signature of this batch (pointers, sizes, plans, fold depths, T)
   std::vector<uint64_t> key;
-  key.reserve(4 + 6 * (size_t)count);
+  key.reserve(4 + 6 * (size_t)count);  // (fold depth | strip height << 32) per grid
   key.push_back((uint64_t)device);
   key.push_back((uint64_t)T);
   key.push_back(use_graph ? 1 : 0);
@@ -818,14 +842,15 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
     key.push_back((uint64_t)(uintptr_t)grids[i].scratch);
     key.push_back((uint64_t)grids[i].shape[0]);
     key.push_back((uint64_t)grids[i].shape[1]);
-    key.push_back((uint64_t)m_of[i]);
+    key.push_back((uint64_t)m_of[i] | ((uint64_t)rows_of[i] << 32));
   }
   auto hit = std::find_if(g_cache.begin(), g_cache.end(),
                           [&](const BatchEntry &b) { return b.key == key; });
   if (hit == g_cache.end()) {
     BatchEntry b;
     b.key = key;
-    if (int rc = build_entry(plans, grids, count, T, m_of, use_graph, device, b)) return rc;
+    if (int rc = build_entry(plans, grids, count, T, m_of, rows_of, use_graph, device, b))
+      return rc;
     g_cache.push_front(b);
     if (g_cache.size() > kCacheEntries) {
       free_entry(g_cache.back());
