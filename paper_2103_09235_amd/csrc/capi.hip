@@ -567,6 +567,27 @@ struct Schedule {
   bool final_copy = false;
 };
 
+// The zero-padded copy a zero-boundary run works on: pad P = m*r on the
+// grid's axes, rows rounded up to whole 256-byte lines; np = extents, off =
+// the interior's first index per axis (z, y, x).
+Geom padded_geom(stencil_plan p, const Geom &geo, int dtype, int64_t np[3], int64_t off[3]) {
+  const int64_t P = (int64_t)p->m * p->r;
+  const int64_t n[3] = {geo.nz, geo.ny, geo.nx};
+  for (int a = 0; a < 3; ++a) {
+    const bool axis = a >= 3 - p->dim;
+    off[a] = axis ? P : 0;
+    np[a] = axis ? n[a] + 2 * P : 1;
+  }
+  const int64_t line = 256 / (int64_t)esize(dtype);
+  np[2] = (np[2] + line - 1) / line * line;
+  Geom pg;
+  pg.dim = p->dim;
+  pg.nz = np[0];
+  pg.ny = np[1];
+  pg.nx = np[2];
+  return pg;
+}
+
 Schedule make_schedule(stencil_plan p, const Geom &geo, int dtype, const void *data,
                        const void *scratch, int64_t T) {
   Schedule sc;
@@ -584,16 +605,25 @@ Schedule make_schedule(stencil_plan p, const Geom &geo, int dtype, const void *d
     L.g = geo;
     L.dtype = dtype;
     L.op = &op;
-    if (p->boundary != STENCIL_PERIODIC)
-      kmax[i] = 1;  // the zero pad is restored after every application
-    else if (p->dim == 1 && p->mode != STENCIL_MODE_EXACT_ORDER)
+    if (p->boundary != STENCIL_PERIODIC) {
+      // plain applications of 2D FP32 VECTOR plans fuse on the padded grid,
+      // each stage zeroing the pad; folded ones restore it one by one
+      kmax[i] = 1;
+      if (i == 1 && p->dim == 2 && dtype == STENCIL_F32 && p->mode == STENCIL_MODE_VECTOR) {
+        int64_t np[3], off[3];
+        L.g = padded_geom(p, geo, dtype, np, off);
+        kmax[i] = std::max(1, sweep2d_max_steps(L));
+      }
+    } else if (p->dim == 1 && p->mode != STENCIL_MODE_EXACT_ORDER)
       kmax[i] = std::max(1, sweep1d_max_steps(L));
     else if (p->dim == 2 && p->mode == STENCIL_MODE_VECTOR && aligned)
       kmax[i] = std::max(1, sweep2d_max_steps(L));
     if (p->max_fuse > 0) kmax[i] = std::min<int64_t>(kmax[i], p->max_fuse);
     sc.launches[i] = (sc.apps[i] + kmax[i] - 1) / kmax[i];
   }
-  for (int i = 0; i < 2; ++i) {
+  // an even launch count saves the final copy (zero-boundary runs always
+  // copy the padded result back)
+  for (int i = 0; i < 2 && p->boundary == STENCIL_PERIODIC; ++i) {
     if ((sc.launches[0] + sc.launches[1]) % 2 == 0) break;
     if (kmax[i] > 1 && sc.launches[i] < sc.apps[i]) sc.launches[i] += 1;
   }
@@ -607,23 +637,17 @@ Schedule make_schedule(stencil_plan p, const Geom &geo, int dtype, const void *d
 // whole 256-byte lines), each application runs the periodic kernels on the
 // padded grid, then restores the zero pad; a folded application also
 // recomputes the band closer than (m-1)r to a face from m plain steps on a
-// frame of width 2(m-1)r.  The result is copied back into g->data; g->scratch
-// is not used.
+// frame of width 2(m-1)r.  Plain applications of 2D FP32 VECTOR plans fuse
+// several per launch, the fused kernel zeroing the pad at every stage.  The
+// result is copied back into g->data; g->scratch is not used.
 int run_dirichlet(stencil_plan p, stencil_grid *g, int64_t T, const Geom &geo, DeviceState &d) {
-  const int dim = p->dim, m = p->m, r = p->r;
+  const int m = p->m, r = p->r;
   const int dtype = g->dtype;
   const size_t es = esize(dtype);
-  const int64_t P = (int64_t)m * r;
   const int64_t n[3] = {geo.nz, geo.ny, geo.nx};
   int64_t np[3], off[3];
-  for (int a = 0; a < 3; ++a) {
-    const bool axis = a >= 3 - dim;
-    off[a] = axis ? P : 0;
-    np[a] = axis ? n[a] + 2 * P : 1;
-  }
   // padded rows in whole 256-byte lines (aligned row segments for the tiles)
-  const int64_t line = 256 / (int64_t)es;
-  np[2] = (np[2] + line - 1) / line * line;
+  const Geom pg = padded_geom(p, geo, dtype, np, off);
   const size_t bytes = (size_t)(np[0] * np[1] * np[2]) * es;
   if (d.dir_bytes < bytes) {
     if (d.dir_bytes) STENCIL_HIP_TRY(hipDeviceSynchronize());
@@ -647,24 +671,35 @@ int run_dirichlet(stencil_plan p, stencil_grid *g, int64_t T, const Geom &geo, D
   for (void *b : {A, F[0], F[1]})
     if (e == hipSuccess) e = dirichlet_clear_pad(b, np, off, n, dtype, s);
   if (e != hipSuccess) return hip_fail(e, "zero-boundary set-up");
-  Geom pg;
-  pg.dim = dim;
-  pg.nz = np[0];
-  pg.ny = np[1];
-  pg.nx = np[2];
   SweepLaunch L;
   L.g = pg;
   L.dtype = dtype;
   L.stream = s;
   L.steps = 1;
-  const int64_t q = m > 1 ? T / m : 0;
-  const int64_t rem = m > 1 ? T % m : T;
+  const Schedule sc = make_schedule(p, geo, dtype, g->data, g->data, T);
+  const int64_t q = sc.apps[0];
   const int64_t Wb = (int64_t)(m - 1) * r, Wf = 2 * Wb;
-  for (int64_t k = 0; k < q + rem; ++k) {
+  int64_t left = sc.apps[1];  // plain applications still to launch
+  const int64_t nl = q + sc.launches[1];
+  for (int64_t k = 0; k < nl; ++k) {
     const bool fold = k < q;
     L.op = fold ? &folded : &plain;
     L.in = A;
     L.out = B;
+    L.steps = 1;
+    L.zb = false;
+    if (!fold) {
+      // plain applications spread evenly over the remaining launches
+      L.steps = (int)((left + (nl - k) - 1) / (nl - k));
+      left -= L.steps;
+      if (L.steps > 1) {
+        L.zb = true;
+        L.zbox[0] = (int)off[1];
+        L.zbox[1] = (int)(off[1] + n[1]);
+        L.zbox[2] = (int)off[2];
+        L.zbox[3] = (int)(off[2] + n[2]);
+      }
+    }
     e = dispatch(p, L);
     if (e == hipSuccess && fold && m > 1) {
       // levels 1 .. m-1 on the frame, level m into the band of B
@@ -675,7 +710,8 @@ int run_dirichlet(stencil_plan p, stencil_grid *g, int64_t T, const Geom &geo, D
       }
       if (e == hipSuccess) e = dirichlet_frame_step(src, B, np, off, n, Wb, plain, dtype, s);
     }
-    if (e == hipSuccess) e = dirichlet_clear_pad(B, np, off, n, dtype, s);
+    // a fused launch leaves the pad zero; the others restore it
+    if (e == hipSuccess && !L.zb) e = dirichlet_clear_pad(B, np, off, n, dtype, s);
     if (e != hipSuccess) return hip_fail(e, "zero-boundary sweep");
     std::swap(A, B);
   }

@@ -18,6 +18,10 @@
 // stored.  Every stored value went through K plain steps in the canonical
 // order (acc = +0, one FMA per tap, offsets row-major), so the result equals
 // K plain sweeps bit for bit.
+//
+// ZB (zero boundary): the grid is a zero-padded copy (pad >= R on every
+// face); each stage sets its output to 0 outside the interior box, so every
+// level is the zero-ghost sweep's and the pad stays zero.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -61,10 +65,12 @@ __device__ __forceinline__ float lane_from_right(float x) {
                                                                 0x130, 0xF, 0xF, true));
 }
 
-template <int R, int MASK, int K>
-__global__ void __launch_bounds__(64)
-k_sweep2d_tb(const float *__restrict__ in, float *__restrict__ out, int ny, int nx, int BY,
-             int tiles_x, WArr<float, (2 * R + 1) * (2 * R + 1)> W) {
+// One strip (tile t).  ZB: zero every stage's output outside zbox.
+template <int R, int MASK, int K, bool ZB>
+__device__ __forceinline__ void tb_body(const float *__restrict__ in, float *__restrict__ out,
+                                        int ny, int nx, int BY, int tiles_x,
+                                        const WArr<float, (2 * R + 1) * (2 * R + 1)> &W,
+                                        int4 zbox, int t) {
   constexpr int S = 2 * R + 1;
   constexpr int NU = S;                        // queue length = unroll of the row loop
   constexpr int B = border(K, R);
@@ -73,7 +79,6 @@ k_sweep2d_tb(const float *__restrict__ in, float *__restrict__ out, int ny, int 
   static_assert(R <= kVX, "halo columns come from the two neighbouring lanes");
 
   const int lane = threadIdx.x;
-  const int t = xcd_contiguous(blockIdx.x, gridDim.x);
   const int tx = t % tiles_x, ty = t / tiles_x;
   const int xo0 = tx * WOUT;     // first stored column of the strip
   const int xi0 = xo0 - B;       // first loaded column (a multiple of 4)
@@ -84,6 +89,15 @@ k_sweep2d_tb(const float *__restrict__ in, float *__restrict__ out, int ny, int 
   // Stored lanes: four columns inside [B, kSpan - B) and inside the grid.
   const int lo = kVX * lane - B;
   const bool store_ok = lo >= 0 && lo + kVX <= WOUT && xo0 + lo + kVX <= nx;
+  // ZB: the lane's columns inside the interior box (zbox = rows [x, y),
+  // columns [z, w)).  Indices are taken unwrapped: a column or row past the
+  // pad lies outside the grid too, where every value is 0.
+  bool col_in[kVX];
+#pragma unroll
+  for (int v = 0; v < kVX; ++v)
+    col_in[v] = !ZB || (xi0 + kVX * lane + v >= zbox.z && xi0 + kVX * lane + v < zbox.w);
+  // most strips hold no pad column: their rows are masked whole (uniform)
+  const bool cols_in = !ZB || (xi0 >= zbox.z && xi0 + kSpan <= zbox.w);
 
   float acc[K][NU][kVX];
 #pragma unroll
@@ -130,6 +144,15 @@ k_sweep2d_tb(const float *__restrict__ in, float *__restrict__ out, int ny, int 
       }
 #pragma unroll
       for (int v = 0; v < kVX; ++v) cur[v] = acc[s][u % NU][v];
+      if constexpr (ZB) {
+        // level-(s+1) row j - (s+1)R: zero outside the interior box
+        const int yr = j - (s + 1) * R;
+        const bool row_in = yr >= zbox.x && yr < zbox.y;
+        if (!cols_in || !row_in) {
+#pragma unroll
+          for (int v = 0; v < kVX; ++v) cur[v] = (row_in && col_in[v]) ? cur[v] : 0.0f;
+        }
+      }
     }
     const int yd = j - K * R;  // level-K row just completed
     if (store_ok && yd >= y0 && yd < y1) store_vec<float, kVX>(out + (size_t)yd * nx + xo0 + lo, cur);
@@ -160,6 +183,18 @@ k_sweep2d_tb(const float *__restrict__ in, float *__restrict__ out, int ny, int 
   }
 }
 
+// All strips of a launch are resident at once (one per wavefront slot), so
+// the launch lasts as long as its slowest strip: a zero-boundary launch runs
+// the masked body in every strip (an unmasked body for the strips that hold
+// no pad cell measured no faster).
+template <int R, int MASK, int K, bool ZB>
+__global__ void __launch_bounds__(64)
+k_sweep2d_tb(const float *__restrict__ in, float *__restrict__ out, int ny, int nx, int BY,
+             int tiles_x, WArr<float, (2 * R + 1) * (2 * R + 1)> W, int4 zbox) {
+  tb_body<R, MASK, K, ZB>(in, out, ny, nx, BY, tiles_x, W, zbox,
+                          xcd_contiguous(blockIdx.x, gridDim.x));
+}
+
 // Wavefront slots the device holds at once for a kernel (one wave per block).
 template <typename F>
 int resident_blocks(F kernel) {
@@ -175,6 +210,9 @@ int resident_blocks(F kernel) {
 
 template <int R, int MASK, int K>
 hipError_t launch_one(const SweepLaunch &L) {
+  if (L.zb && (L.zbox[0] < R || L.zbox[2] < R || (int)L.g.ny - L.zbox[1] < R ||
+               (int)L.g.nx - L.zbox[3] < R))
+    return hipErrorInvalidValue;  // the pad must hold every read of the interior
   constexpr int S = 2 * R + 1;
   constexpr int WOUT = kSpan - 2 * border(K, R);
   WArr<float, S * S> W;
@@ -190,7 +228,7 @@ hipError_t launch_one(const SweepLaunch &L) {
     // One strip per resident wavefront slot, each as tall as that allows
     // (a second round of strips measured slower than taller strips, whose
     // 2KR redundant rows cost less); at least 4KR rows.
-    static const int slots = resident_blocks(k_sweep2d_tb<R, MASK, K>);
+    static const int slots = resident_blocks(k_sweep2d_tb<R, MASK, K, false>);
     const int tiles_y = std::max(1, slots / tiles_x);
     by = std::max((ny + tiles_y - 1) / tiles_y, 4 * K * R);
   }
@@ -198,8 +236,13 @@ hipError_t launch_one(const SweepLaunch &L) {
   const int tiles_y = (ny + by - 1) / by;
   const int64_t blocks = (int64_t)tiles_x * tiles_y;
   if (blocks > (1LL << 31) - 1) return hipErrorNotSupported;
-  hipLaunchKernelGGL((k_sweep2d_tb<R, MASK, K>), dim3((unsigned)blocks), dim3(64), 0, L.stream,
-                     (const float *)L.in, (float *)L.out, ny, nx, by, tiles_x, W);
+  const int4 zbox = {L.zbox[0], L.zbox[1], L.zbox[2], L.zbox[3]};
+  if (L.zb)
+    hipLaunchKernelGGL((k_sweep2d_tb<R, MASK, K, true>), dim3((unsigned)blocks), dim3(64), 0,
+                       L.stream, (const float *)L.in, (float *)L.out, ny, nx, by, tiles_x, W, zbox);
+  else
+    hipLaunchKernelGGL((k_sweep2d_tb<R, MASK, K, false>), dim3((unsigned)blocks), dim3(64), 0,
+                       L.stream, (const float *)L.in, (float *)L.out, ny, nx, by, tiles_x, W, zbox);
   return hipGetLastError();
 }
 

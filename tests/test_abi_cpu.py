@@ -203,11 +203,17 @@ def test_run_schedule_counts_launches():
     w4 = synth.random_positive_weights(2, 4, mask=synth.star_mask(2, 4))
     s = _sched(sf.Plan(w4, sf.STENCIL_STAR), (8192, 8192), 1001)
     assert (s["plain_launches"], s["final_copy"]) == (502, False)
-    # zero-boundary plans: any axis >= 1, no fusion, always a copy back
+    # zero-boundary plans: any axis >= 1, always a copy back; plain 2D FP32
+    # applications fuse on the padded grid (no even split needed), folded
+    # ones and narrow padded grids do not
     dstar = sf.Plan(synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR, sf.STENCIL_DIRICHLET)
     s = _sched(dstar, (8192, 8192), 16)
-    assert (s["plain_launches"], s["final_copy"]) == (16, True)
+    assert (s["plain_launches"], s["final_copy"]) == (2, True)
+    s = _sched(dstar, (8192, 8192), 13)
+    assert (s["plain_launches"], s["final_copy"]) == (2, True)
     assert _sched(dstar, (1, 2), 3)["plain_launches"] == 3
+    assert _sched(dstar, (100, 100), 10)["plain_launches"] == 10
+    assert _sched(dstar, (8192, 8192), 10, sf.STENCIL_F64)["plain_launches"] == 10
     # boxes of radius 3 and more are not fused (FMA-issue bound already)
     b3 = synth.random_positive_weights(2, 3)
     assert _sched(sf.Plan(b3, sf.STENCIL_BOX), (8192, 8192), 10)["plain_launches"] == 10

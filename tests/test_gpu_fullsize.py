@@ -197,6 +197,34 @@ def test_dirichlet_sampled_outputs_full_size():
         assert abs(got - ref) <= 1e-5 * abs(ref), (p, got, ref)
 
 
+def test_dirichlet_plain_fused_full_size():
+    """Zero boundaries, plain sweep at the measured size (8192^2, T = 24: two
+    launches of 12 fused steps on the padded grid): sampled points, corners
+    and edges included, against the FP64 zero-ghost oracle on the point's
+    window clipped to the grid."""
+    wl = synth.WORKLOADS["star2d_dirichlet"]
+    u0 = full_grid("star2d")
+    T = 24
+    plan = sf.Plan(wl.weights, wl.shape_kind, sf.STENCIL_DIRICHLET)
+    d = torch.from_numpy(u0).to(DEV)
+    sched = plan.schedule(d, T)
+    assert sched["plain_launches"] == 2
+    plan.run(d, T)
+    torch.cuda.synchronize()
+    plan.close()
+    ny, nx = wl.shape
+    pts = sampled_points(wl.shape, 30, zlib.crc32(b"star2d_dirichlet_plain"))
+    pts += [(0, 0), (0, nx - 1), (ny - 1, 0), (ny - 1, nx - 1), (5, nx // 3), (ny // 3, nx - 2)]
+    reach = T * 1
+    for p in pts:
+        y0, y1 = max(0, p[0] - reach), min(ny, p[0] + reach + 1)
+        x0, x1 = max(0, p[1] - reach), min(nx, p[1] + reach + 1)
+        win = u0[y0:y1, x0:x1].astype(np.float64)
+        ref = oracle.sweep(wl.weights, win, T, "zero")[p[0] - y0, p[1] - x0]
+        got = d[p].item()
+        assert abs(got - ref) <= 1e-5 * abs(ref), (p, got, ref)
+
+
 def test_apop_full_size_sampled_bit_exact():
     """APOP at its Table 1 size (10,240,000 points, FP64), 40 steps fused as
     the library runs them: sampled points bit-exact against the oracle's loop

@@ -503,6 +503,17 @@ DIR_CASES = [
     ("one_row", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (1, 9), 5, 2, "f32"),
     ("star3d_m2", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (12, 14, 18), 5, 2, "f32"),
     ("box3d_plain", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (9, 10, 11), 3, 1, "f32"),
+    # plain 2D FP32 applications fused on the padded grid (pad zeroed at
+    # every stage): depths 10/9, 6/5, the 3-step remainder of a fold, and
+    # the fewest padded rows a depth-12 star fuses with
+    ("star2d_plain_fused", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (70, 300), 29, 1,
+     "f32"),
+    ("box2d_plain_fused", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (40, 260), 17, 1,
+     "f32"),
+    ("star2d_m4_rem3_fused", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (64, 256), 19, 4,
+     "f32"),
+    ("star2d_fused_min_rows", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (23, 510), 24, 1,
+     "f32"),
 ]
 
 
