@@ -546,8 +546,35 @@ def bench_batched(args):
         p.close()
     if not args.no_cpu:
         log("[bench] timing the CPU oracle baseline")
-        res["cpu_baseline"] = cpu_baseline(weights[0], (1024, 1024), "f32", T, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline_batched(weights, u0s, T, args.cpu_seconds)
     return res
+
+
+def cpu_baseline_batched(weights, grids, T, budget_s):
+    """The oracle on the batch itself: grids in batch order, each advanced by
+    all T steps, until about budget_s seconds have been spent."""
+    import numpy as np
+    import oracle
+    oracle.sweep(weights[0], grids[0].astype(np.float64), 1)  # warm: threads
+    pts = 0
+    spent = 0.0
+    k = 0
+    while k < len(grids) and spent < budget_s:
+        u0 = grids[k].astype(np.float64)
+        t0 = time.perf_counter()
+        oracle.sweep(weights[k], u0, T)
+        spent += time.perf_counter() - t0
+        pts += u0.size
+        k += 1
+    return {
+        "value": round(pts * T / spent / 1e9, 4),
+        "unit": "GStencil/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": "FP64 naive sweep of the batch's first %d grids (%d points, sides %d..%d), "
+                  "all %d steps each, %.1f s" % (k, pts, min(g.shape[0] for g in grids[:k]),
+                                                 max(g.shape[0] for g in grids[:k]), T, spent),
+    }
 
 
 def bench_apop(args):
