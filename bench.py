@@ -327,6 +327,16 @@ def bench_grid(args, wl_name):
                     gst, launches, per_launch, launch_ms, err, err_detr,
                     "n/a" if mass_rel is None else "%.2e" % mass_rel))
             forms[key]["stated_fold"] = m not in extra
+            if mode_name == "mfma_bf16x3":
+                # matrix-core work issued: per dy three 16x16x32 products
+                # (hi*hi, hi*lo, lo*hi) per 16x16 output block, 64 flop per
+                # point each, over 2R+1 values of dy
+                Rf = m * ((w.shape[0] - 1) // 2)
+                issued = 3 * (2 * Rf + 1) * 64.0 * n * per_launch
+                forms[key]["mfma_issued_flop_per_point"] = int(3 * (2 * Rf + 1) * 64)
+                forms[key]["mfma_issued_tflops"] = round(issued / (launch_ms / 1e3) / 1e12, 1)
+                forms[key]["mfma_util_of_bf16_peak"] = round(
+                    issued / (launch_ms / 1e3) / 1e12 / BF16_MFMA_TFLOPS, 4)
             if m not in extra and (headline is None or gst > headline[1]):
                 headline = (key, gst, el, launch_ms, algo_bytes, flops, m, mode_name, taps,
                             per_launch)
