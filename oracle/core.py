@@ -41,6 +41,12 @@ def _load():
     lib.oracle_sweep_bc_f32.argtypes = [ctypes.c_int, i64p, ctypes.c_int, fp, fp,
                                         ctypes.c_int64, ctypes.c_int, fp]
     lib.oracle_sweep_bc_f32.restype = ctypes.c_int
+    lib.oracle_sweep_gv_f64.argtypes = [ctypes.c_int, i64p, ctypes.c_int, dp, dp,
+                                        ctypes.c_int64, ctypes.c_int, ctypes.c_double, dp]
+    lib.oracle_sweep_gv_f64.restype = ctypes.c_int
+    lib.oracle_sweep_gv_f32.argtypes = [ctypes.c_int, i64p, ctypes.c_int, fp, fp,
+                                        ctypes.c_int64, ctypes.c_int, ctypes.c_float, fp]
+    lib.oracle_sweep_gv_f32.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -70,41 +76,43 @@ def _radius_of(w: np.ndarray, dim: int) -> int:
 BOUNDARIES = {"periodic": 0, "zero": 1}
 
 
-def sweep(w, u0, T: int, boundary: str = "periodic") -> np.ndarray:
+def sweep(w, u0, T: int, boundary: str = "periodic", ghost: float = 0.0) -> np.ndarray:
     """u_T = A^T u_0 in FP64 (paper, Section 1: the naive (d+1)-loop stencil,
     time outermost; canonical FMA order).  boundary "periodic" wraps every
-    axis; "zero" holds every point outside the grid at 0 (Dirichlet ghosts;
-    the paper states no boundary, so both are readings)."""
+    axis; "zero" holds every point outside the grid at the value ghost, 0 by
+    default (Dirichlet ghosts; the paper states no boundary, so both are
+    readings)."""
     u0 = np.ascontiguousarray(u0, dtype=np.float64)
     w = np.ascontiguousarray(w, dtype=np.float64)
     dim = u0.ndim
     r = _radius_of(w, dim)
     shape = (ctypes.c_int64 * dim)(*u0.shape)
     out = np.empty_like(u0)
-    rc = _load().oracle_sweep_bc_f64(
+    rc = _load().oracle_sweep_gv_f64(
         dim, shape, r, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
         u0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(T), BOUNDARIES[boundary],
-        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        float(ghost), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     if rc != 0:
-        raise ValueError("oracle_sweep_bc_f64 rejected its arguments")
+        raise ValueError("oracle_sweep_gv_f64 rejected its arguments")
     return out
 
 
-def sweep_f32(w32, u0, T: int, boundary: str = "periodic") -> np.ndarray:
-    """The same loop and operation order in FP32 (fmaf): the bit-exact
-    reference for kernels that keep the canonical order."""
+def sweep_f32(w32, u0, T: int, boundary: str = "periodic", ghost: float = 0.0) -> np.ndarray:
+    """The same loop and operation order in FP32 (fmaf; the ghost value
+    rounded to FP32): the bit-exact reference for kernels that keep the
+    canonical order."""
     u0 = np.ascontiguousarray(u0, dtype=np.float32)
     w32 = np.ascontiguousarray(w32, dtype=np.float32)
     dim = u0.ndim
     r = _radius_of(w32, dim)
     shape = (ctypes.c_int64 * dim)(*u0.shape)
     out = np.empty_like(u0)
-    rc = _load().oracle_sweep_bc_f32(
+    rc = _load().oracle_sweep_gv_f32(
         dim, shape, r, w32.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
         u0.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(T), BOUNDARIES[boundary],
-        out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        float(np.float32(ghost)), out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
     if rc != 0:
-        raise ValueError("oracle_sweep_bc_f32 rejected its arguments")
+        raise ValueError("oracle_sweep_gv_f32 rejected its arguments")
     return out
 
 
@@ -254,16 +262,19 @@ def band_mask(shape, width: int) -> np.ndarray:
     return mask
 
 
-def dirichlet_folded(w, u0, T: int, m: int, f32: bool = False) -> np.ndarray:
-    """Folding with zero Dirichlet ghosts (a reading: the paper states no
-    boundary).  Each of the floor(T/m) folded applications (Section 3.3) uses
-    W_m with zero ghosts at points at least (m-1)r from every face, where no
-    path of the m plain steps it replaces passes through a ghost (the j-th
-    intermediate point of a path lies within j*r of the output), and takes m
-    plain zero-ghost steps of w in the band closer than (m-1)r; the T mod m
-    remaining steps are plain.  In exact arithmetic this is sweep(w, u0, T,
-    "zero").  f32: the FP32 mirror (FP32 folded weights, canonical order),
-    the bit-exact reference of the library's canonical-order kernels."""
+def dirichlet_folded(w, u0, T: int, m: int, f32: bool = False, ghost: float = 0.0) -> np.ndarray:
+    """Folding with Dirichlet ghosts of value ghost, 0 by default (a reading:
+    the paper states no boundary).  Each of the floor(T/m) folded
+    applications (Section 3.3) uses W_m (its taps outside the grid reading
+    the ghost value) at points at least (m-1)r from every face, where no
+    intermediate point of the m plain steps it replaces lies outside the grid
+    (the j-th intermediate point of a path lies within j*r of the output; only
+    the final reads of the initial state reach the ghosts, which hold the
+    same value at every step), and takes m plain steps of w in the band closer
+    than (m-1)r; the T mod m remaining steps are plain.  In exact arithmetic
+    this is sweep(w, u0, T, "zero", ghost).  f32: the FP32 mirror (FP32
+    folded weights and ghost, canonical order), the bit-exact reference of the
+    library's canonical-order kernels."""
     q, s = schedule(T, m)
     w = np.asarray(w, dtype=np.float64)
     r = (w.shape[0] - 1) // 2
@@ -275,9 +286,9 @@ def dirichlet_folded(w, u0, T: int, m: int, f32: bool = False) -> np.ndarray:
         Wm, w1, run = fold_weights(w, m), w, sweep
     band = band_mask(u.shape, (m - 1) * r)
     for _ in range(q):
-        u = np.where(band, run(w1, u, m, "zero"), run(Wm, u, 1, "zero"))
+        u = np.where(band, run(w1, u, m, "zero", ghost), run(Wm, u, 1, "zero", ghost))
     if s:
-        u = run(w1, u, s, "zero")
+        u = run(w1, u, s, "zero", ghost)
     return u
 
 

@@ -121,14 +121,18 @@ static void free_taps(taps_t *t) {
 }
 
 /*
- * oracle_sweep_bc_f64: u_T = A^T u_0 with the canonical FMA chain, FP64.
+ * oracle_sweep_gv_f64: u_T = A^T u_0 with the canonical FMA chain, FP64.
  * dim in {1,2,3}; shape[dim] in numpy order (slowest first, x last);
  * w dense (2r+1)^dim; u0 and out hold prod(shape) values (they may alias);
- * boundary 0 = periodic, 1 = zero Dirichlet ghosts.
+ * boundary 0 = periodic, 1 = Dirichlet ghosts: every point outside the grid
+ * holds the value ghost at every step.  A tap on a ghost is skipped when
+ * ghost is 0 (it would add a zero product) and is an FMA with ghost, in its
+ * place in the chain, otherwise.
  * Returns 0, or -1 on bad arguments / allocation failure.
  */
-int oracle_sweep_bc_f64(int dim, const int64_t *shape, int r, const double *w,
-                        const double *u0, int64_t T, int boundary, double *out) {
+int oracle_sweep_gv_f64(int dim, const int64_t *shape, int r, const double *w,
+                        const double *u0, int64_t T, int boundary, double ghost,
+                        double *out) {
   geom_t g;
   if (make_geom(dim, shape, r, &g) || T < 0 || boundary < 0 || boundary > 1) return -1;
   int64_t N = g.n[0] * g.n[1] * g.n[2];
@@ -152,7 +156,10 @@ int oracle_sweep_bc_f64(int dim, const int64_t *shape, int r, const double *w,
             int64_t zz = tz[z + taps.oz[k] + g.rad[0]];
             int64_t yy = ty[y + taps.oy[k] + g.rad[1]];
             int64_t xx = tx[x + taps.ox[k] + g.rad[2]];
-            if (zz < 0 || yy < 0 || xx < 0) continue; /* zero ghost */
+            if (zz < 0 || yy < 0 || xx < 0) { /* ghost */
+              if (ghost != 0.0) acc = fma(w[taps.widx[k]], ghost, acc);
+              continue;
+            }
             acc = fma(w[taps.widx[k]], a[(zz * ny + yy) * nx + xx], acc);
           }
           b[(z * ny + y) * nx + x] = acc;
@@ -174,11 +181,12 @@ done:
 }
 
 /*
- * oracle_sweep_f32: the same definition and operation order in FP32 (fmaf).
- * Weights are FP32 as the kernels hold them.
+ * oracle_sweep_gv_f32: the same definition and operation order in FP32
+ * (fmaf).  Weights and the ghost value are FP32 as the kernels hold them.
  */
-int oracle_sweep_bc_f32(int dim, const int64_t *shape, int r, const float *w,
-                        const float *u0, int64_t T, int boundary, float *out) {
+int oracle_sweep_gv_f32(int dim, const int64_t *shape, int r, const float *w,
+                        const float *u0, int64_t T, int boundary, float ghost,
+                        float *out) {
   geom_t g;
   if (make_geom(dim, shape, r, &g) || T < 0 || boundary < 0 || boundary > 1) return -1;
   int64_t N = g.n[0] * g.n[1] * g.n[2];
@@ -207,7 +215,10 @@ int oracle_sweep_bc_f32(int dim, const int64_t *shape, int r, const float *w,
             int64_t zz = tz[z + taps.oz[k] + g.rad[0]];
             int64_t yy = ty[y + taps.oy[k] + g.rad[1]];
             int64_t xx = tx[x + taps.ox[k] + g.rad[2]];
-            if (zz < 0 || yy < 0 || xx < 0) continue; /* zero ghost */
+            if (zz < 0 || yy < 0 || xx < 0) { /* ghost */
+              if (ghost != 0.0f) acc = fmaf(w[taps.widx[k]], ghost, acc);
+              continue;
+            }
             acc = fmaf(w[taps.widx[k]], a[(zz * ny + yy) * nx + xx], acc);
           }
           b[(z * ny + y) * nx + x] = acc;
@@ -227,6 +238,17 @@ done:
   free(ty);
   free(tx);
   return rc;
+}
+
+/* Periodic (boundary 0) or zero-ghost (boundary 1) sweeps. */
+int oracle_sweep_bc_f64(int dim, const int64_t *shape, int r, const double *w,
+                        const double *u0, int64_t T, int boundary, double *out) {
+  return oracle_sweep_gv_f64(dim, shape, r, w, u0, T, boundary, 0.0, out);
+}
+
+int oracle_sweep_bc_f32(int dim, const int64_t *shape, int r, const float *w,
+                        const float *u0, int64_t T, int boundary, float *out) {
+  return oracle_sweep_gv_f32(dim, shape, r, w, u0, T, boundary, 0.0f, out);
 }
 
 /* The periodic sweeps (boundary 0). */

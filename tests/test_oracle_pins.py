@@ -581,6 +581,94 @@ def test_dirichlet_pins_catch_a_narrow_band():
     assert not np.array_equal(u, oracle.sweep(w, u0, T, "zero"))
 
 
+def brute_force_ghost(w, u0, T, ghost):
+    """A^T u0 for Dirichlet ghosts of value ghost: each step sums the taps
+    inside the grid over the current values and the taps outside over the
+    ghost value (the affine map u -> A_0 u + ghost * b), exact arithmetic."""
+    shape = u0.shape
+    dim = len(shape)
+    r = (w.shape[0] - 1) // 2
+    rows, outs = [], []
+    for x in itertools.product(*[range(n) for n in shape]):
+        row, out = {}, 0
+        for o in itertools.product(range(-r, r + 1), repeat=dim):
+            wo = w[tuple(oi + r for oi in o)]
+            col = tuple(xi + oi for xi, oi in zip(x, o))
+            if any(c < 0 or c >= n for c, n in zip(col, shape)):
+                out += wo
+            elif wo != 0:
+                row[int(np.ravel_multi_index(col, shape))] = wo
+        rows.append(row)
+        outs.append(out)
+    vec = list(u0.ravel())
+    for _ in range(T):
+        vec = [sum(wv * vec[c] for c, wv in row.items()) + ghost * b for row, b in zip(rows, outs)]
+    return np.array(vec, dtype=object).reshape(shape)
+
+
+@pytest.mark.parametrize("shape", [(1,), (4,), (9,), (1, 1), (3, 4), (6, 5), (2, 3, 4)])
+@pytest.mark.parametrize("r", [1, 2])
+def test_ghost_value_brute_force_integer_bit_exact(shape, r):
+    """Dirichlet ghosts of a nonzero value: integer weights, values and
+    ghost, exact against the affine brute force."""
+    g = rng(zlib.crc32(repr((shape, r, "ghost")).encode()))
+    w = g.integers(-3, 4, size=(2 * r + 1,) * len(shape)).astype(np.float64)
+    u0 = g.integers(-5, 6, size=shape).astype(np.float64)
+    ghost = int(g.integers(-4, 5)) or 3
+    T = 3
+    ref = brute_force_ghost(w.astype(int).astype(object), u0.astype(int).astype(object), T, ghost)
+    got = oracle.sweep(w, u0, T, "zero", ghost)
+    assert np.array_equal(got, ref.astype(np.float64))
+    assert np.array_equal(oracle.sweep_f32(w, u0, T, "zero", ghost), ref.astype(np.float32))
+
+
+def test_ghost_value_affine_shift_exact():
+    """Weights summing to 1: holding the ghosts at c is the zero-ghost sweep
+    of u0 - c, shifted by c (exact with dyadic weights and values)."""
+    w = synth.heat1d_weights()
+    w2 = np.outer([0.25, 0.5, 0.25], [0.25, 0.5, 0.25])
+    g = rng(77)
+    for wt, shape in ((w, (23,)), (w2, (9, 12))):
+        u0 = g.integers(0, 16, size=shape).astype(np.float64)
+        c = 3.0
+        for T in (1, 4, 7):
+            got = oracle.sweep(wt, u0, T, "zero", c)
+            assert np.array_equal(got, oracle.sweep(wt, u0 - c, T, "zero") + c)
+
+
+def test_ghost_value_constant_field_stays():
+    """A field equal to the ghost value everywhere stays at it (weights
+    summing to 1, dyadic), in FP64 and in the FP32 mirror."""
+    w2 = np.outer([0.25, 0.5, 0.25], [0.25, 0.5, 0.25])
+    u0 = np.full((7, 10), 2.5)
+    assert np.array_equal(oracle.sweep(w2, u0, 9, "zero", 2.5), u0)
+    assert np.array_equal(oracle.sweep_f32(w2, u0.astype(np.float32), 9, "zero", 2.5),
+                          u0.astype(np.float32))
+
+
+@pytest.mark.parametrize("dim,r,m,shape", [(1, 1, 3, (14,)), (2, 1, 2, (9, 14)), (2, 1, 4, (17, 30)),
+                                           (2, 2, 3, (23, 11)), (3, 1, 2, (6, 7, 9))])
+def test_ghost_value_folding_reading_exact(dim, r, m, shape):
+    """The folded reading with ghosts of a nonzero value equals the plain
+    sweep exactly on integer data."""
+    g = rng(dim * 1000 + r * 10 + m)
+    w = g.integers(-2, 3, size=(2 * r + 1,) * dim).astype(np.float64)
+    u0 = g.integers(-4, 5, size=shape).astype(np.float64)
+    for T in (m, 2 * m + 1):
+        assert np.array_equal(oracle.dirichlet_folded(w, u0, T, m, ghost=-2.0),
+                              oracle.sweep(w, u0, T, "zero", -2.0))
+
+
+def test_ghost_value_pin_catches_a_dropped_ghost():
+    """Ignoring the ghost value (zero ghosts, planted here) fails the brute
+    force the pins above use."""
+    w = np.array([[0, 1, 0], [2, 3, 1], [0, 2, 0]])
+    u0 = (np.arange(4 * 5).reshape(4, 5) % 7)
+    ref = brute_force_ghost(w.astype(object), u0.astype(object), 2, 5)
+    planted = oracle.sweep(w.astype(np.float64), u0.astype(np.float64), 2, "zero", 0.0)
+    assert not np.array_equal(planted, ref.astype(np.float64))
+
+
 def test_dirichlet_mirror_f32_close_to_fp64():
     w = synth.WORKLOADS["star2d"].weights
     u0 = synth.grid_f32((40, 52))
