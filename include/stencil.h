@@ -163,6 +163,20 @@ int stencil_plan_set_mode(stencil_plan p, int mode);
 int stencil_plan_set_fusion(stencil_plan p, int max_steps);
 
 /*
+ * stencil_plan_set_boundary_value -- the value every point outside the grid
+ * holds at every step for a STENCIL_DIRICHLET plan (0 by default; the paper
+ * states no boundary, so the boundary and its value are readings).  A tap
+ * on a ghost adds weight * value in its place in the canonical chain (a zero
+ * value adds nothing).  FP32 runs use the value rounded to FP32.  Folded
+ * applications stay exact: a point at least (m-1)r from every face reaches
+ * the ghosts only through the initial state of the m steps it replaces, and
+ * the band nearer the faces takes m plain steps.
+ * Errors: E_ARG (not finite), E_UNSUPPORTED (a nonzero value on a periodic
+ * plan).  No device work.
+ */
+int stencil_plan_set_boundary_value(stencil_plan p, double value);
+
+/*
  * stencil_plan_set_graph -- 1 = stencil_run records the launches of a
  * periodic run (the time loop of Section 1: floor(T/m) folded and T mod m
  * plain applications, plus the final copy of an odd launch count) once in a

@@ -32,6 +32,7 @@ STENCIL_E_STATE = -5
 EXPORTS = (
     "stencil_plan_create", "stencil_fold_weights", "stencil_fold_weights_f32",
     "stencil_plan_set_mode", "stencil_plan_set_fusion", "stencil_plan_set_graph",
+    "stencil_plan_set_boundary_value",
     "stencil_plan_separable",
     "stencil_plan_set_floor", "stencil_life", "stencil_life_launches",
     "stencil_plan_info",
@@ -91,6 +92,7 @@ def _load() -> ctypes.CDLL:
     lib.stencil_plan_set_mode.argtypes = [P, ctypes.c_int]
     lib.stencil_plan_set_fusion.argtypes = [P, ctypes.c_int]
     lib.stencil_plan_set_graph.argtypes = [P, ctypes.c_int]
+    lib.stencil_plan_set_boundary_value.argtypes = [P, ctypes.c_double]
     lib.stencil_plan_separable.argtypes = [P, ip, ip]
     lib.stencil_plan_set_floor.argtypes = [P, P, ctypes.c_int, ctypes.c_int64]
     lib.stencil_life.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, P]
@@ -168,6 +170,10 @@ def stencil_plan_set_fusion(plan, max_steps: int) -> None:
 
 def stencil_plan_set_graph(plan, on: bool) -> None:
     _check(lib.stencil_plan_set_graph(plan, int(bool(on))))
+
+
+def stencil_plan_set_boundary_value(plan, value: float) -> None:
+    _check(lib.stencil_plan_set_boundary_value(plan, float(value)))
 
 
 def stencil_plan_separable(plan):
@@ -363,6 +369,9 @@ class Plan:
 
     def set_graph(self, on: bool) -> None:
         stencil_plan_set_graph(self.handle, on)
+
+    def set_boundary_value(self, value: float) -> None:
+        stencil_plan_set_boundary_value(self.handle, value)
 
     def separable(self):
         return stencil_plan_separable(self.handle)

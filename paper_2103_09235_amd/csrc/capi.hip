@@ -470,6 +470,16 @@ int stencil_plan_set_fusion(stencil_plan p, int max_steps) {
   return STENCIL_OK;
 }
 
+int stencil_plan_set_boundary_value(stencil_plan p, double value) {
+  set_error("");
+  if (int rc = check_plan(p)) return rc;
+  if (!std::isfinite(value)) return fail(STENCIL_E_ARG, "the boundary value must be finite");
+  if (p->boundary != STENCIL_DIRICHLET && value != 0.0)
+    return fail(STENCIL_E_UNSUPPORTED, "a boundary value needs a STENCIL_DIRICHLET plan");
+  p->bvalue = value;
+  return STENCIL_OK;
+}
+
 int stencil_plan_set_graph(stencil_plan p, int on) {
   set_error("");
   if (int rc = check_plan(p)) return rc;
@@ -669,7 +679,7 @@ int run_dirichlet(stencil_plan p, stencil_grid *g, int64_t T, const Geom &geo, D
                                     np[2], n, dtype, s);
   // pads cleared on every run: the buffers may hold another geometry's data
   for (void *b : {A, F[0], F[1]})
-    if (e == hipSuccess) e = dirichlet_clear_pad(b, np, off, n, dtype, s);
+    if (e == hipSuccess) e = dirichlet_clear_pad(b, np, off, n, dtype, p->bvalue, s);
   if (e != hipSuccess) return hip_fail(e, "zero-boundary set-up");
   SweepLaunch L;
   L.g = pg;
@@ -694,6 +704,7 @@ int run_dirichlet(stencil_plan p, stencil_grid *g, int64_t T, const Geom &geo, D
       left -= L.steps;
       if (L.steps > 1) {
         L.zb = true;
+        L.zval = p->bvalue;
         L.zbox[0] = (int)off[1];
         L.zbox[1] = (int)(off[1] + n[1]);
         L.zbox[2] = (int)off[2];
@@ -711,7 +722,7 @@ int run_dirichlet(stencil_plan p, stencil_grid *g, int64_t T, const Geom &geo, D
       if (e == hipSuccess) e = dirichlet_frame_step(src, B, np, off, n, Wb, plain, dtype, s);
     }
     // a fused launch leaves the pad zero; the others restore it
-    if (e == hipSuccess && !L.zb) e = dirichlet_clear_pad(B, np, off, n, dtype, s);
+    if (e == hipSuccess && !L.zb) e = dirichlet_clear_pad(B, np, off, n, dtype, p->bvalue, s);
     if (e != hipSuccess) return hip_fail(e, "zero-boundary sweep");
     std::swap(A, B);
   }

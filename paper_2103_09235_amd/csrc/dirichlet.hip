@@ -1,5 +1,8 @@
-// Zero Dirichlet boundaries (every point outside the grid holds 0) for plain
-// and folded sweeps.  The paper states no boundary; the reading here:
+// Dirichlet boundaries (every point outside the grid holds a fixed ghost
+// value, 0 by default) for plain and folded sweeps.  The paper states no
+// boundary; the reading here (with 0; a nonzero ghost value fills the pad
+// instead, and the same argument holds since the ghosts keep their value at
+// every step):
 //
 //  * A run works on zero-padded copies of the grid (pad P = m*r on every
 //    face of the grid's axes).  Any periodic kernel of the library applied to
@@ -150,12 +153,12 @@ __global__ void k_frame_step(const T *__restrict__ src, T *__restrict__ dst, Pad
   }
 }
 
-// Clear every pad point of a padded array: one wavefront per padded row
-// (stores only).
+// Set every pad point of a padded array to the ghost value: one wavefront
+// per padded row (stores only).
 constexpr int kRowsPerBlock = 4;
 
 template <typename T>
-__global__ void k_clear_pad(T *__restrict__ dst, PadGeom g) {
+__global__ void k_clear_pad(T *__restrict__ dst, PadGeom g, T value) {
   const int64_t prow = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (prow >= g.np[0] * g.np[1]) return;
@@ -163,12 +166,12 @@ __global__ void k_clear_pad(T *__restrict__ dst, PadGeom g) {
   T *d = dst + prow * g.np[2];
   const int64_t z = pz - g.off[0], y = py - g.off[1];
   if (z < 0 || z >= g.n[0] || y < 0 || y >= g.n[1]) {
-    for (int64_t px = lane; px < g.np[2]; px += 64) d[px] = T(0);
+    for (int64_t px = lane; px < g.np[2]; px += 64) d[px] = value;
     return;
   }
   const int64_t right = g.off[2] + g.n[2];
   const int64_t npad = g.off[2] + (g.np[2] - right);
-  for (int64_t i = lane; i < npad; i += 64) d[i < g.off[2] ? i : right + (i - g.off[2])] = T(0);
+  for (int64_t i = lane; i < npad; i += 64) d[i < g.off[2] ? i : right + (i - g.off[2])] = value;
 }
 
 int blocks_for(int64_t n, int threads) {
@@ -224,16 +227,16 @@ hipError_t dirichlet_frame_step(const void *src, void *dst, const int64_t np[3],
 }
 
 hipError_t dirichlet_clear_pad(void *dst, const int64_t np[3], const int64_t off[3],
-                               const int64_t n[3], int dtype, hipStream_t s) {
+                               const int64_t n[3], int dtype, double value, hipStream_t s) {
   const PadGeom g = pad_geom(np, off, n);
   const int64_t blocks = (np[0] * np[1] + kRowsPerBlock - 1) / kRowsPerBlock;
   if (blocks > (1LL << 31) - 1) return hipErrorNotSupported;
   if (dtype == STENCIL_F32)
     hipLaunchKernelGGL(k_clear_pad<float>, dim3((unsigned)blocks), dim3(64 * kRowsPerBlock), 0,
-                       s, (float *)dst, g);
+                       s, (float *)dst, g, (float)value);
   else
     hipLaunchKernelGGL(k_clear_pad<double>, dim3((unsigned)blocks), dim3(64 * kRowsPerBlock), 0,
-                       s, (double *)dst, g);
+                       s, (double *)dst, g, value);
   return hipGetLastError();
 }
 

@@ -75,6 +75,7 @@ struct DeviceState {
 struct stencil_plan_s {
   int dim = 0, r = 0, shape = 0, boundary = 0, mode = STENCIL_MODE_VECTOR;
   int max_fuse = 0;           // steps one launch may fuse; 0 = library choice
+  double bvalue = 0.0;        // Dirichlet ghost value
   int use_graph = 0;          // 1 = replay periodic runs from captured hipGraphs
   const void *floor = nullptr;  // caller's floor array (device), or none
   int floor_dtype = 0;
@@ -130,6 +131,7 @@ struct SweepLaunch {
   // [zbox[2], zbox[3]) are 0, as the zero ghosts of the unpadded grid.
   bool zb = false;
   int zbox[4] = {0, 0, 0, 0};
+  double zval = 0.0;  // the ghost value the box's outside holds
   hipStream_t stream = nullptr;
 };
 
@@ -167,8 +169,9 @@ hipError_t dirichlet_box_copy(const void *src, int64_t sbase, int64_t ssz, int64
 hipError_t dirichlet_frame_step(const void *src, void *dst, const int64_t np[3],
                                 const int64_t off[3], const int64_t n[3], int64_t W,
                                 const OperatorDev &op, int dtype, hipStream_t s);
+// Set every pad point of a padded array to the ghost value.
 hipError_t dirichlet_clear_pad(void *dst, const int64_t np[3], const int64_t off[3],
-                               const int64_t n[3], int dtype, hipStream_t s);
+                               const int64_t n[3], int dtype, double value, hipStream_t s);
 
 // FP64 fold convolution: out = a (radius Ra) * w (radius r), dim d.
 hipError_t launch_fold_conv(const double *a, int Ra, const double *w, int r,

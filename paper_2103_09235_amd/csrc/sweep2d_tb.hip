@@ -19,9 +19,10 @@
 // order (acc = +0, one FMA per tap, offsets row-major), so the result equals
 // K plain sweeps bit for bit.
 //
-// ZB (zero boundary): the grid is a zero-padded copy (pad >= R on every
-// face); each stage sets its output to 0 outside the interior box, so every
-// level is the zero-ghost sweep's and the pad stays zero.
+// ZB (Dirichlet boundary): the grid is a padded copy (pad >= R on every
+// face) holding the ghost value; each stage sets its output to that value
+// outside the interior box, so every level is the Dirichlet sweep's and the
+// pad keeps its value.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -70,7 +71,7 @@ template <int R, int MASK, int K, bool ZB>
 __device__ __forceinline__ void tb_body(const float *__restrict__ in, float *__restrict__ out,
                                         int ny, int nx, int BY, int tiles_x,
                                         const WArr<float, (2 * R + 1) * (2 * R + 1)> &W,
-                                        int4 zbox, int t) {
+                                        int4 zbox, float zval, int t) {
   constexpr int S = 2 * R + 1;
   constexpr int NU = S;                        // queue length = unroll of the row loop
   constexpr int B = border(K, R);
@@ -150,7 +151,7 @@ __device__ __forceinline__ void tb_body(const float *__restrict__ in, float *__r
         const bool row_in = yr >= zbox.x && yr < zbox.y;
         if (!cols_in || !row_in) {
 #pragma unroll
-          for (int v = 0; v < kVX; ++v) cur[v] = (row_in && col_in[v]) ? cur[v] : 0.0f;
+          for (int v = 0; v < kVX; ++v) cur[v] = (row_in && col_in[v]) ? cur[v] : zval;
         }
       }
     }
@@ -190,8 +191,8 @@ __device__ __forceinline__ void tb_body(const float *__restrict__ in, float *__r
 template <int R, int MASK, int K, bool ZB>
 __global__ void __launch_bounds__(64)
 k_sweep2d_tb(const float *__restrict__ in, float *__restrict__ out, int ny, int nx, int BY,
-             int tiles_x, WArr<float, (2 * R + 1) * (2 * R + 1)> W, int4 zbox) {
-  tb_body<R, MASK, K, ZB>(in, out, ny, nx, BY, tiles_x, W, zbox,
+             int tiles_x, WArr<float, (2 * R + 1) * (2 * R + 1)> W, int4 zbox, float zval) {
+  tb_body<R, MASK, K, ZB>(in, out, ny, nx, BY, tiles_x, W, zbox, zval,
                           xcd_contiguous(blockIdx.x, gridDim.x));
 }
 
@@ -239,10 +240,12 @@ hipError_t launch_one(const SweepLaunch &L) {
   const int4 zbox = {L.zbox[0], L.zbox[1], L.zbox[2], L.zbox[3]};
   if (L.zb)
     hipLaunchKernelGGL((k_sweep2d_tb<R, MASK, K, true>), dim3((unsigned)blocks), dim3(64), 0,
-                       L.stream, (const float *)L.in, (float *)L.out, ny, nx, by, tiles_x, W, zbox);
+                       L.stream, (const float *)L.in, (float *)L.out, ny, nx, by, tiles_x, W, zbox,
+                       (float)L.zval);
   else
     hipLaunchKernelGGL((k_sweep2d_tb<R, MASK, K, false>), dim3((unsigned)blocks), dim3(64), 0,
-                       L.stream, (const float *)L.in, (float *)L.out, ny, nx, by, tiles_x, W, zbox);
+                       L.stream, (const float *)L.in, (float *)L.out, ny, nx, by, tiles_x, W, zbox,
+                       0.0f);
   return hipGetLastError();
 }
 

@@ -102,6 +102,14 @@ def test_plan_info_mode_and_profitability():
     p.set_graph(False)
     assert sf.lib.stencil_plan_set_graph(p.handle, 2) == sf.STENCIL_E_ARG
     assert sf.lib.stencil_plan_set_graph(None, 1) == sf.STENCIL_E_ARG
+    # boundary values: Dirichlet plans only, finite
+    p.set_boundary_value(0.0)
+    assert sf.lib.stencil_plan_set_boundary_value(p.handle, 1.5) == sf.STENCIL_E_UNSUPPORTED
+    d = sf.Plan(synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR, sf.STENCIL_DIRICHLET)
+    d.set_boundary_value(-2.25)
+    assert sf.lib.stencil_plan_set_boundary_value(d.handle, float("nan")) == sf.STENCIL_E_ARG
+    assert sf.lib.stencil_plan_set_boundary_value(d.handle, float("inf")) == sf.STENCIL_E_ARG
+    d.close()
 
 
 def test_plan_f32_weights_start_unfolded():

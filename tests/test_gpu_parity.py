@@ -517,13 +517,15 @@ DIR_CASES = [
 ]
 
 
-def _run_dirichlet(w, kind, u0, T, m, mode=sf.STENCIL_MODE_VECTOR, plan=None):
+def _run_dirichlet(w, kind, u0, T, m, mode=sf.STENCIL_MODE_VECTOR, plan=None, ghost=None):
     own = plan is None
     if own:
         plan = sf.Plan(w, kind, sf.STENCIL_DIRICHLET)
         if m > 1:
             plan.fold(m)
         plan.set_mode(mode)
+        if ghost is not None:
+            plan.set_boundary_value(ghost)
     data = torch.from_numpy(np.ascontiguousarray(u0)).to(DEV)
     plan.run(data, T)
     torch.cuda.synchronize()
@@ -573,6 +575,73 @@ def test_dirichlet_other_modes(mode, gate):
     else:
         ref64 = oracle.sweep(w, u0.astype(np.float64), T, "zero")
         assert oracle.errors(got, ref64)["e_rel"] < gate
+
+
+# ghost values: one exact in FP32, one rounded to FP32 on both sides
+GHOSTS = {"heat1d_plain_f64": 0.3, "heat1d_m3_f32": -1.75, "star2d_plain": 0.3,
+          "star2d_m4": -1.75, "star2d_m2_f64": -1.75, "box2d_m2": 0.3, "box2d_m8": 2.5,
+          "tiny_band_everywhere": 0.3, "one_row": -1.75, "star3d_m2": 0.3, "box3d_plain": -1.75,
+          "star2d_plain_fused": 0.3, "box2d_plain_fused": -1.75, "star2d_m4_rem3_fused": 2.5,
+          "star2d_fused_min_rows": -1.75}
+
+
+@pytest.mark.parametrize("case", DIR_CASES, ids=lambda c: c[0])
+def test_dirichlet_ghost_value_bit_exact(case):
+    """Ghosts of a nonzero value (the pad filled with it, the fused kernels
+    writing it at every stage): bit for bit the oracle's folded reading with
+    the same ghost, and the FP64 sweep with that ghost within the gate."""
+    name, w, kind, shape, T, m, dt = case
+    c = GHOSTS[name]
+    print("dirichlet ghost", name, shape, "T", T, "m", m, dt, "ghost", c, flush=True)
+    if dt == "f32":
+        w = synth.to_f32_exact(w)
+        u0 = synth.grid_f32(shape)
+    else:
+        u0 = synth.grid_f64(shape)
+    got = _run_dirichlet(w, kind, u0, T, m, ghost=c)
+    if dt == "f32":
+        assert np.array_equal(got, oracle.dirichlet_folded(w, u0, T, m, f32=True, ghost=c))
+        ref64 = oracle.sweep(w, u0.astype(np.float64), T, "zero", float(np.float32(c)))
+        assert oracle.errors(got, ref64)["e_rel"] < 1e-5
+    else:
+        assert np.array_equal(got, oracle.dirichlet_folded(w, u0, T, m, ghost=c))
+        ref64 = oracle.sweep(w, u0, T, "zero", c)
+        assert oracle.errors(got, ref64)["e_rel"] < 1e-13
+
+
+@pytest.mark.parametrize("mode,gate", [("exact", 0.0), ("symmetric", 1e-5), ("separable", 1e-5),
+                                       ("mfma", 1e-3)])
+def test_dirichlet_ghost_value_other_modes(mode, gate):
+    w = np.full((3, 3), 1.0 / 9.0) if mode == "separable" else synth.WORKLOADS["star2d"].weights
+    if mode == "mfma":
+        w = synth.WORKLOADS["box2d"].weights
+    w = synth.to_f32_exact(w)
+    kind = sf.STENCIL_STAR if mode in ("exact", "symmetric") else sf.STENCIL_BOX
+    code = {"exact": sf.STENCIL_MODE_EXACT_ORDER, "symmetric": sf.STENCIL_MODE_SYMMETRIC,
+            "separable": sf.STENCIL_MODE_SEPARABLE, "mfma": sf.STENCIL_MODE_MFMA_BF16X3}[mode]
+    u0 = synth.grid_f32((70, 256))
+    T, m, c = 11, 4, -1.25
+    print("dirichlet ghost mode", mode, flush=True)
+    got = _run_dirichlet(w, kind, u0, T, m, code, ghost=c)
+    if gate == 0.0:
+        assert np.array_equal(got, oracle.dirichlet_folded(w, u0, T, m, f32=True, ghost=c))
+    else:
+        ref64 = oracle.sweep(w, u0.astype(np.float64), T, "zero", c)
+        assert oracle.errors(got, ref64)["e_rel"] < gate
+
+
+def test_dirichlet_ghost_value_changed_on_a_plan():
+    """A plan's ghost value can change between runs: the pads of the kept
+    buffers are refilled on every run."""
+    w = synth.to_f32_exact(synth.WORKLOADS["star2d"].weights)
+    plan = sf.Plan(w, sf.STENCIL_STAR, sf.STENCIL_DIRICHLET)
+    plan.fold(2)
+    u0 = synth.grid_f32((48, 300))
+    for c in (1.5, 0.0, -0.5):
+        plan.set_boundary_value(c)
+        got = _run_dirichlet(w, sf.STENCIL_STAR, u0, 9, 2, plan=plan)
+        assert np.array_equal(got, oracle.dirichlet_folded(w, u0, 9, 2, f32=True, ghost=c)), c
+    plan.close()
 
 
 def test_dirichlet_plan_reused_across_geometries():
