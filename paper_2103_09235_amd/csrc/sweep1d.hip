@@ -3,16 +3,26 @@
 //
 // A 1D grid of a few million points is far too small to keep HBM busy for a
 // single step (1e6 FP64 points are 16 MB of traffic, about 2 us at HBM
-// rate, less than a kernel launch), so one launch advances its block of the
-// line k steps: the block loads its 64*4*VX-point span plus k*R halo points
-// on each side, every lane keeps VX consecutive points in registers, and
-// each step swaps R edge values with the neighbouring lanes through LDS.
-// Values near the span's ends go stale by R points per step; the k*R points
-// at each end are exactly that stale region and are never stored.  This is
-// the GPU counterpart of the paper's tiling in time (Section 3.4, tessellate
-// tiling: several steps per tile without reloading), done here with
-// overlapping spans instead of triangles, which costs 2kR redundant points
-// per span but needs no second phase.
+// rate, less than a kernel launch), so one launch advances each span of the
+// line k steps: the span's owner loads its points plus k*R halo points on
+// each side, every lane keeps VX consecutive points in registers, and each
+// step takes R edge values from each neighbouring lane.  Values near the
+// span's ends go stale by R points per step; the k*R points at each end are
+// exactly that stale region and are never stored.  This is the GPU
+// counterpart of the paper's tiling in time (Section 3.4, tessellate tiling:
+// several steps per tile without reloading), done here with overlapping
+// spans instead of triangles, which costs 2kR redundant points per span but
+// needs no second phase.
+//
+// Two owners of a span:
+// * a workgroup of 256 lanes (spans of 256*VX points) exchanging edge values
+//   through LDS, one barrier per step: long spans, so few redundant points
+//   and many steps per launch, for lines with enough spans to keep several
+//   wavefronts on every SIMD, which hide the barrier;
+// * a single wavefront (spans of 64*VX points) exchanging edge values with
+//   DPP lane shifts, no LDS and no barrier: for short lines (1e6 points fill
+//   about one wavefront per SIMD), where every step's LDS round trip and
+//   barrier would sit on the critical path of the only wavefront a SIMD has.
 //
 // Every step of every point is the plain update in canonical order
 // (acc = +0, one FMA per tap, offsets ascending), so results are
@@ -22,6 +32,9 @@
 // drop below the exercise payoff) every step ends with u = maxNum(u, floor)
 // at each point; the lane keeps its points' floor values in registers.
 #include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
 
 #include "internal.h"
 
@@ -42,6 +55,141 @@ __device__ __forceinline__ double fma1(double a, double b, double c) { return __
 __device__ __forceinline__ float max1(float a, float b) { return __builtin_fmaxf(a, b); }
 __device__ __forceinline__ double max1(double a, double b) { return __builtin_fmax(a, b); }
 
+// VX consecutive points from index base on (periodic: indices wrap mod n,
+// any number of times for a line shorter than the span).
+template <typename T, int VX, bool FLOOR>
+__device__ __forceinline__ void load_wrapped(const T *__restrict__ in, const T *__restrict__ floor,
+                                             int64_t n, int64_t base, T (&cur)[VX],
+                                             T (&fl)[VX]) {
+  int64_t g = base % n;
+  if (g < 0) g += n;
+#pragma unroll
+  for (int v = 0; v < VX; ++v) {
+    cur[v] = in[g];
+    if constexpr (FLOOR) fl[v] = floor[g];
+    if (++g == n) g = 0;
+  }
+}
+
+// One step of a lane's VX points given the R values left and right of them.
+template <typename T, int R, int VX, bool FLOOR>
+__device__ __forceinline__ void step_points(T (&cur)[VX], const T (&fl)[VX], const T (&lnb)[R],
+                                            const T (&rnb)[R], const WArr1<T, 2 * R + 1> &W) {
+  T nxt[VX];
+#pragma unroll
+  for (int v = 0; v < VX; ++v) {
+    T acc = T(0);
+#pragma unroll
+    for (int o = -R; o <= R; ++o) {
+      const int p = v + o;
+      const T x = p < 0 ? lnb[R + p] : (p >= VX ? rnb[p - VX] : cur[p]);
+      acc = fma1(W.v[o + R], x, acc);
+    }
+    nxt[v] = FLOOR ? max1(acc, fl[v]) : acc;
+  }
+#pragma unroll
+  for (int v = 0; v < VX; ++v) cur[v] = nxt[v];
+}
+
+// Whole-wavefront DPP shifts by one lane (lane i receives lane i-1's value,
+// or lane i+1's; the end lanes receive 0, which lands in the stale halo).
+__device__ __forceinline__ int dpp_from_left(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true);
+}
+__device__ __forceinline__ int dpp_from_right(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, true);
+}
+__device__ __forceinline__ float from_left(float x) {
+  return __builtin_bit_cast(float, dpp_from_left(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ float from_right(float x) {
+  return __builtin_bit_cast(float, dpp_from_right(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double from_left(double x) {
+  const int2 h = __builtin_bit_cast(int2, x);
+  return __builtin_bit_cast(double, make_int2(dpp_from_left(h.x), dpp_from_left(h.y)));
+}
+__device__ __forceinline__ double from_right(double x) {
+  const int2 h = __builtin_bit_cast(int2, x);
+  return __builtin_bit_cast(double, make_int2(dpp_from_right(h.x), dpp_from_right(h.y)));
+}
+
+// Orders a wavefront's LDS writes before its later reads (lanes of one
+// wavefront only; no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Index of span point i in a wavefront's LDS tile: one pad slot per 16
+// points, so lanes reading 16 consecutive points each (stride 17) hit
+// distinct banks.
+__device__ __forceinline__ int tile_at(int i) { return i + (i >> 4); }
+
+// A lane's VX consecutive points (from span point lane*VX on) of the
+// 64*VX-point span starting at global index base0 (periodic wrap): the
+// wavefront reads 64 consecutive points per load instruction into its LDS
+// tile, then each lane reads its own points back.
+template <typename T, int VX>
+__device__ __forceinline__ void gather_span(const T *__restrict__ src, int64_t n, int64_t base0,
+                                            int lane, T *tile, T (&dst)[VX]) {
+  int64_t g = (base0 + lane) % n;
+  if (g < 0) g += n;
+#pragma unroll
+  for (int v = 0; v < VX; ++v) {
+    tile[tile_at(64 * v + lane)] = src[g];
+    g += 64;
+    while (g >= n) g -= n;
+  }
+  wave_sync();
+#pragma unroll
+  for (int v = 0; v < VX; ++v) dst[v] = tile[tile_at(lane * VX + v)];
+  wave_sync();
+}
+
+// The wavefront-owned span: wavefront wv of the grid owns points
+// [wv*span_out, (wv+1)*span_out) and loads 64*VX points from k*R before.
+template <typename T, int R, int VX, bool FLOOR>
+__global__ void __launch_bounds__(kThreads)
+k_sweep1d_wave(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
+               int64_t span_out, int64_t spans, WArr1<T, 2 * R + 1> W,
+               const T *__restrict__ floor) {
+  static_assert(VX >= R, "neighbour values must come from the adjacent lane");
+  __shared__ T tiles[kThreads / 64][64 * VX + 4 * VX];
+  const int lane = threadIdx.x & 63;
+  const int64_t wv = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (wv >= spans) return;  // whole wavefronts only; no workgroup barrier below
+  T *tile = tiles[threadIdx.x >> 6];
+  const int64_t out0 = wv * span_out;
+  const int64_t halo = (int64_t)k * R;
+
+  T cur[VX], fl[VX];
+  gather_span<T, VX>(in, n, out0 - halo, lane, tile, cur);
+  if constexpr (FLOOR) gather_span<T, VX>(floor, n, out0 - halo, lane, tile, fl);
+  for (int s = 0; s < k; ++s) {
+    T lnb[R], rnb[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      lnb[i] = from_left(cur[VX - R + i]);  // value at position -R + i
+      rnb[i] = from_right(cur[i]);          // value at position VX + i
+    }
+    step_points<T, R, VX, FLOOR>(cur, fl, lnb, rnb, W);
+  }
+  // back through the tile: 64 consecutive points per store instruction
+#pragma unroll
+  for (int v = 0; v < VX; ++v) tile[tile_at(lane * VX + v)] = cur[v];
+  wave_sync();
+#pragma unroll
+  for (int v = 0; v < VX; ++v) {
+    const int i = 64 * v + lane;  // index within the loaded span
+    if (i >= halo && i < halo + span_out) {
+      const int64_t g = out0 + (i - halo);
+      if (g < n) out[g] = tile[tile_at(i)];
+    }
+  }
+}
+
 template <typename T, int R, int VX, bool FLOOR>
 __global__ void __launch_bounds__(kThreads)
 k_sweep1d(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
@@ -54,13 +202,7 @@ k_sweep1d(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
   const int64_t base = out0 - halo + (int64_t)t * VX;    // first point of this lane
 
   T cur[VX], fl[VX];
-#pragma unroll
-  for (int v = 0; v < VX; ++v) {
-    int64_t g = (base + v) % n;
-    if (g < 0) g += n;
-    cur[v] = in[g];
-    if constexpr (FLOOR) fl[v] = floor[g];
-  }
+  load_wrapped<T, VX, FLOOR>(in, floor, n, base, cur, fl);
 
   for (int s = 0; s < k; ++s) {
     const int b = s & 1;
@@ -78,20 +220,7 @@ k_sweep1d(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
       lnb[i] = edge[b][1][tl][i];  // value at position -R + i
       rnb[i] = edge[b][0][tr][i];  // value at position VX + i
     }
-    T nxt[VX];
-#pragma unroll
-    for (int v = 0; v < VX; ++v) {
-      T acc = T(0);
-#pragma unroll
-      for (int o = -R; o <= R; ++o) {
-        const int p = v + o;
-        const T x = p < 0 ? lnb[R + p] : (p >= VX ? rnb[p - VX] : cur[p]);
-        acc = fma1(W.v[o + R], x, acc);
-      }
-      nxt[v] = FLOOR ? max1(acc, fl[v]) : acc;
-    }
-#pragma unroll
-    for (int v = 0; v < VX; ++v) cur[v] = nxt[v];
+    step_points<T, R, VX, FLOOR>(cur, fl, lnb, rnb, W);
   }
 
 #pragma unroll
@@ -104,30 +233,63 @@ k_sweep1d(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
   }
 }
 
-template <typename T>
-constexpr int vx_of() {
-  return sizeof(T) == 8 ? 16 : 16;
+constexpr int kVX = 16;                        // points per lane
+constexpr int64_t kSpanGroup = kThreads * kVX;   // span of the workgroup-owned kernel
+constexpr int64_t kSpanWave = 64 * kVX;          // span of the wavefront-owned kernel
+
+// Steps per launch: the workgroup span keeps its redundant halo work (2kR
+// of the span) near 5%; the wavefront span allows 10%, since its steps cost
+// little beside the launch's own read and write of the line.
+int64_t max_steps_for(int64_t span, int R) {
+  const int64_t div = span == kSpanWave ? 20 : 40;
+  return std::max<int64_t>(1, span / (div * (int64_t)R));
+}
+
+// The wavefront-owned kernel while the line has at most about four
+// wavefront spans per SIMD (256 CUs x 4 SIMDs); STENCIL_1D_KERNEL=wave or
+// group forces one (read once per process).
+bool use_wave_kernel(int64_t n, int R) {
+  static const int forced = [] {
+    const char *e = std::getenv("STENCIL_1D_KERNEL");
+    if (!e) return 0;
+    if (!std::strcmp(e, "wave")) return 1;
+    if (!std::strcmp(e, "group")) return 2;
+    return 0;
+  }();
+  if (forced) return forced == 1;
+  const int64_t out = kSpanWave - 2 * max_steps_for(kSpanWave, R) * R;
+  return (n + out - 1) / out <= 4 * 1024;
 }
 
 template <typename T, int R>
 hipError_t launch_r(const SweepLaunch &L, const std::vector<T> &w) {
-  constexpr int VX = vx_of<T>();
   WArr1<T, 2 * R + 1> W;
   for (int i = 0; i < 2 * R + 1; ++i) W.v[i] = w[i];
-  const int64_t span = (int64_t)kThreads * VX;
+  const int64_t n = L.g.nx;
+  const bool wave = use_wave_kernel(n, R);
+  const int64_t span = wave ? kSpanWave : kSpanGroup;
   const int64_t span_out = span - 2 * (int64_t)L.steps * R;
   if (span_out < 1) return hipErrorNotSupported;
-  const int64_t n = L.g.nx;
-  const int64_t blocks = (n + span_out - 1) / span_out;
+  const int64_t spans = (n + span_out - 1) / span_out;
+  const int64_t blocks = wave ? (spans + kThreads / 64 - 1) / (kThreads / 64) : spans;
   if (blocks > (1LL << 31) - 1) return hipErrorNotSupported;
-  if (L.floor)
-    hipLaunchKernelGGL((k_sweep1d<T, R, VX, true>), dim3((unsigned)blocks), dim3(kThreads), 0,
-                       L.stream, (const T *)L.in, (T *)L.out, n, L.steps, span_out, W,
-                       (const T *)L.floor);
-  else
-    hipLaunchKernelGGL((k_sweep1d<T, R, VX, false>), dim3((unsigned)blocks), dim3(kThreads), 0,
-                       L.stream, (const T *)L.in, (T *)L.out, n, L.steps, span_out, W,
-                       (const T *)nullptr);
+  const T *fl = (const T *)L.floor;
+  if (wave) {
+    if (fl)
+      hipLaunchKernelGGL((k_sweep1d_wave<T, R, kVX, true>), dim3((unsigned)blocks),
+                         dim3(kThreads), 0, L.stream, (const T *)L.in, (T *)L.out, n, L.steps,
+                         span_out, spans, W, fl);
+    else
+      hipLaunchKernelGGL((k_sweep1d_wave<T, R, kVX, false>), dim3((unsigned)blocks),
+                         dim3(kThreads), 0, L.stream, (const T *)L.in, (T *)L.out, n, L.steps,
+                         span_out, spans, W, fl);
+  } else if (fl) {
+    hipLaunchKernelGGL((k_sweep1d<T, R, kVX, true>), dim3((unsigned)blocks), dim3(kThreads), 0,
+                       L.stream, (const T *)L.in, (T *)L.out, n, L.steps, span_out, W, fl);
+  } else {
+    hipLaunchKernelGGL((k_sweep1d<T, R, kVX, false>), dim3((unsigned)blocks), dim3(kThreads), 0,
+                       L.stream, (const T *)L.in, (T *)L.out, n, L.steps, span_out, W, fl);
+  }
   return hipGetLastError();
 }
 
@@ -151,9 +313,7 @@ hipError_t launch_t(const SweepLaunch &L, const std::vector<T> &w) {
 int sweep1d_max_steps(const SweepLaunch &L) {
   const int R = L.op->R;
   if (R < 1 || R > 8) return 1;
-  // keep the redundant halo work (2kR of 256*16 points) near 5%
-  const int64_t span = (int64_t)kThreads * 16;
-  return (int)std::max<int64_t>(1, span / (40 * (int64_t)R));
+  return (int)max_steps_for(use_wave_kernel(L.g.nx, R) ? kSpanWave : kSpanGroup, R);
 }
 
 hipError_t launch_sweep1d(const SweepLaunch &L) {
