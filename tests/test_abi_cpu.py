@@ -231,6 +231,14 @@ def test_run_schedule_counts_launches():
     # 1D fuses many steps per launch; 3D none
     heat = sf.Plan(synth.heat1d_weights(), sf.STENCIL_STAR)
     assert _sched(heat, (1_000_000,), 100, sf.STENCIL_F64)["plain_launches"] < 10
+    # short lines: wavefront spans of 1024 points, at most 51 steps per launch
+    # at radius 1; long lines: workgroup spans of 4096, at most 102 (radius 1)
+    # or 51 (radius 2); an even launch count saves the final copy
+    assert _sched(heat, (1_000_000,), 100, sf.STENCIL_F64)["plain_launches"] == 2
+    assert _sched(heat, (1_000_000,), 200, sf.STENCIL_F64)["plain_launches"] == 4
+    assert _sched(heat, (20_000_000,), 200, sf.STENCIL_F64)["plain_launches"] == 2
+    box5 = sf.Plan(synth.WORKLOADS["box1d5p"].weights, sf.STENCIL_BOX)
+    assert _sched(box5, (10_240_000,), 1000, sf.STENCIL_F64)["plain_launches"] == 20
     box3 = sf.Plan(np.ones((3, 3, 3)) / 27, sf.STENCIL_BOX)
     s = _sched(box3, (64, 64, 64), 5)
     assert (s["plain_launches"], s["final_copy"]) == (5, True)

@@ -141,6 +141,35 @@ def test_heat1d_full_size_bit_exact_fp64():
     assert np.array_equal(d.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("case", [
+    # the 1D5P line (random positive 5-point box, FP64) and a long FP32 heat
+    # line: both run the workgroup-owned 1D kernel (more than four wavefront
+    # spans per SIMD), several steps fused per launch
+    ("box1d5p", 10_240_000, 60, "f64"),
+    ("heat_f32", 6_000_000, 53, "f32"),
+], ids=lambda c: c[0])
+def test_1d_long_line_sampled_bit_exact(case):
+    """Sampled points of a long line, bit-exact against the oracle's sweep of
+    each point's window (2RT+1 points: exact at its centre after T steps)."""
+    name, n, T, dt = case
+    if name == "box1d5p":
+        w, kind = synth.WORKLOADS["box1d5p"].weights, sf.STENCIL_BOX
+    else:
+        w, kind = synth.to_f32_exact(synth.heat1d_weights()), sf.STENCIL_STAR
+    r = (len(w) - 1) // 2
+    u0 = synth.grid_f64((n,)) if dt == "f64" else synth.grid_f32((n,))
+    print("1d long line", name, n, "T", T, dt, flush=True)
+    u = run(w, kind, u0, T, 1).cpu().numpy()
+    for x in sampled_points((n,), 20, zlib.crc32(name.encode())):
+        x = x[0]
+        idx = (x + np.arange(-r * T, r * T + 1)) % n
+        if dt == "f64":
+            ref = oracle.sweep(w, u0[idx], T)[r * T]
+        else:
+            ref = oracle.sweep_f32(w, u0[idx], T)[r * T]
+        assert u[x] == ref, x
+
+
 def test_batched_full_size_sampled_grids(tmp_path):
     """The 4096-grid batch as bench.py runs it (autotuned m <= 2, graph):
     16 grids checked whole against the oracle's FP32 mirror of their fold
