@@ -31,6 +31,12 @@
 // With a floor array (the APOP benchmark of Table 1: option values never
 // drop below the exercise payoff) every step ends with u = maxNum(u, floor)
 // at each point; the lane keeps its points' floor values in registers.
+//
+// Dirichlet boundaries (a padded line whose interior is [zlo, zhi)): every
+// step sets the points outside the interior to the ghost value, their
+// indices taken unwrapped, so points past the pad hold it as well, and the
+// result is the fixed-ghost sweep at every step.  Spans inside the interior
+// skip the test (a uniform branch).
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -89,6 +95,16 @@ __device__ __forceinline__ void step_points(T (&cur)[VX], const T (&fl)[VX], con
   }
 #pragma unroll
   for (int v = 0; v < VX; ++v) cur[v] = nxt[v];
+}
+
+// Dirichlet: a lane's points (unwrapped indices first .. first+VX-1)
+// outside [zlo, zhi) take the ghost value.
+template <typename T, int VX>
+__device__ __forceinline__ void hold_ghosts(T (&cur)[VX], int64_t first, int64_t zlo, int64_t zhi,
+                                            T zval) {
+#pragma unroll
+  for (int v = 0; v < VX; ++v)
+    if (first + v < zlo || first + v >= zhi) cur[v] = zval;
 }
 
 // Whole-wavefront DPP shifts by one lane (lane i receives lane i-1's value,
@@ -154,7 +170,7 @@ template <typename T, int R, int VX, bool FLOOR>
 __global__ void __launch_bounds__(kThreads)
 k_sweep1d_wave(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
                int64_t span_out, int64_t spans, WArr1<T, 2 * R + 1> W,
-               const T *__restrict__ floor) {
+               const T *__restrict__ floor, int zb, int64_t zlo, int64_t zhi, T zval) {
   static_assert(VX >= R, "neighbour values must come from the adjacent lane");
   __shared__ T tiles[kThreads / 64][64 * VX + 4 * VX];
   const int lane = threadIdx.x & 63;
@@ -167,6 +183,8 @@ k_sweep1d_wave(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
   T cur[VX], fl[VX];
   gather_span<T, VX>(in, n, out0 - halo, lane, tile, cur);
   if constexpr (FLOOR) gather_span<T, VX>(floor, n, out0 - halo, lane, tile, fl);
+  const int64_t first = out0 - halo + (int64_t)lane * VX;  // unwrapped
+  const bool edge_span = zb && (out0 - halo < zlo || out0 - halo + 64 * VX > zhi);
   for (int s = 0; s < k; ++s) {
     T lnb[R], rnb[R];
 #pragma unroll
@@ -175,6 +193,7 @@ k_sweep1d_wave(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
       rnb[i] = from_right(cur[i]);          // value at position VX + i
     }
     step_points<T, R, VX, FLOOR>(cur, fl, lnb, rnb, W);
+    if (edge_span) hold_ghosts<T, VX>(cur, first, zlo, zhi, zval);
   }
   // back through the tile: 64 consecutive points per store instruction
 #pragma unroll
@@ -193,7 +212,8 @@ k_sweep1d_wave(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
 template <typename T, int R, int VX, bool FLOOR>
 __global__ void __launch_bounds__(kThreads)
 k_sweep1d(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
-          int64_t span_out, WArr1<T, 2 * R + 1> W, const T *__restrict__ floor) {
+          int64_t span_out, WArr1<T, 2 * R + 1> W, const T *__restrict__ floor, int zb,
+          int64_t zlo, int64_t zhi, T zval) {
   static_assert(VX >= R, "neighbour values must come from the adjacent lane");
   __shared__ T edge[2][2][kThreads][R];  // [buffer][left/right][lane][i]
   const int t = threadIdx.x;
@@ -203,6 +223,7 @@ k_sweep1d(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
 
   T cur[VX], fl[VX];
   load_wrapped<T, VX, FLOOR>(in, floor, n, base, cur, fl);
+  const bool edge_span = zb && (out0 - halo < zlo || out0 - halo + kThreads * VX > zhi);
 
   for (int s = 0; s < k; ++s) {
     const int b = s & 1;
@@ -221,6 +242,7 @@ k_sweep1d(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
       rnb[i] = edge[b][0][tr][i];  // value at position VX + i
     }
     step_points<T, R, VX, FLOOR>(cur, fl, lnb, rnb, W);
+    if (edge_span) hold_ghosts<T, VX>(cur, base, zlo, zhi, zval);
   }
 
 #pragma unroll
@@ -274,21 +296,29 @@ hipError_t launch_r(const SweepLaunch &L, const std::vector<T> &w) {
   const int64_t blocks = wave ? (spans + kThreads / 64 - 1) / (kThreads / 64) : spans;
   if (blocks > (1LL << 31) - 1) return hipErrorNotSupported;
   const T *fl = (const T *)L.floor;
+  // Dirichlet: the interior [zlo, zhi) of the padded line, at least R from
+  // both ends (the ghosts the first step reads are pad points)
+  const int zb = L.zb ? 1 : 0;
+  const int64_t zlo = L.zbox[2], zhi = L.zbox[3];
+  if (zb && (zlo < R || n - zhi < R || zhi <= zlo)) return hipErrorInvalidValue;
+  const T zval = (T)L.zval;
   if (wave) {
     if (fl)
       hipLaunchKernelGGL((k_sweep1d_wave<T, R, kVX, true>), dim3((unsigned)blocks),
                          dim3(kThreads), 0, L.stream, (const T *)L.in, (T *)L.out, n, L.steps,
-                         span_out, spans, W, fl);
+                         span_out, spans, W, fl, zb, zlo, zhi, zval);
     else
       hipLaunchKernelGGL((k_sweep1d_wave<T, R, kVX, false>), dim3((unsigned)blocks),
                          dim3(kThreads), 0, L.stream, (const T *)L.in, (T *)L.out, n, L.steps,
-                         span_out, spans, W, fl);
+                         span_out, spans, W, fl, zb, zlo, zhi, zval);
   } else if (fl) {
     hipLaunchKernelGGL((k_sweep1d<T, R, kVX, true>), dim3((unsigned)blocks), dim3(kThreads), 0,
-                       L.stream, (const T *)L.in, (T *)L.out, n, L.steps, span_out, W, fl);
+                       L.stream, (const T *)L.in, (T *)L.out, n, L.steps, span_out, W, fl, zb,
+                       zlo, zhi, zval);
   } else {
     hipLaunchKernelGGL((k_sweep1d<T, R, kVX, false>), dim3((unsigned)blocks), dim3(kThreads), 0,
-                       L.stream, (const T *)L.in, (T *)L.out, n, L.steps, span_out, W, fl);
+                       L.stream, (const T *)L.in, (T *)L.out, n, L.steps, span_out, W, fl, zb,
+                       zlo, zhi, zval);
   }
   return hipGetLastError();
 }

@@ -514,6 +514,14 @@ DIR_CASES = [
      "f32"),
     ("star2d_fused_min_rows", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (23, 510), 24, 1,
      "f32"),
+    # plain 1D applications fused on the padded line (ghosts written at every
+    # step): wavefront spans, a radius-2 box, the 3-step remainder of a fold,
+    # and a line long enough for the workgroup spans
+    ("heat1d_plain_fused_f32", synth.heat1d_weights(), sf.STENCIL_STAR, (5000,), 60, 1, "f32"),
+    ("box1d_r2_fused_f64", synth.random_positive_weights(1, 2), sf.STENCIL_BOX, (3001,), 23, 1,
+     "f64"),
+    ("heat1d_m4_rem3_fused", synth.heat1d_weights(), sf.STENCIL_STAR, (777,), 15, 4, "f64"),
+    ("heat1d_long_group_f64", synth.heat1d_weights(), sf.STENCIL_STAR, (4_000_000,), 50, 1, "f64"),
 ]
 
 
@@ -582,7 +590,8 @@ GHOSTS = {"heat1d_plain_f64": 0.3, "heat1d_m3_f32": -1.75, "star2d_plain": 0.3,
           "star2d_m4": -1.75, "star2d_m2_f64": -1.75, "box2d_m2": 0.3, "box2d_m8": 2.5,
           "tiny_band_everywhere": 0.3, "one_row": -1.75, "star3d_m2": 0.3, "box3d_plain": -1.75,
           "star2d_plain_fused": 0.3, "box2d_plain_fused": -1.75, "star2d_m4_rem3_fused": 2.5,
-          "star2d_fused_min_rows": -1.75}
+          "star2d_fused_min_rows": -1.75, "heat1d_plain_fused_f32": 0.3, "box1d_r2_fused_f64": -1.75,
+          "heat1d_m4_rem3_fused": 2.5, "heat1d_long_group_f64": 0.3}
 
 
 @pytest.mark.parametrize("case", DIR_CASES, ids=lambda c: c[0])
