@@ -99,11 +99,12 @@ typedef struct {
  *   weights  host, (2r+1)^dim finite FP64 values, copied (the caller may free
  *            them on return).
  *   boundary STENCIL_PERIODIC (every axis wraps) or STENCIL_DIRICHLET (every
- *            point outside the grid holds 0 at every step; the paper states
- *            no boundary, both are readings).  Folded zero-boundary runs
- *            apply W_m at points at least (m-1)r from every face, where it
- *            equals m plain zero-boundary steps exactly, and m plain steps in
- *            the band nearer a face; see stencil_run.
+ *            point outside the grid holds a constant at every step: 0 unless
+ *            stencil_plan_set_boundary_value sets another; the paper states
+ *            no boundary, both are readings).  Folded Dirichlet runs apply
+ *            W_m at points at least (m-1)r from every face, where it equals
+ *            m plain fixed-ghost steps exactly, and m plain steps in the band
+ *            nearer a face; see stencil_run.
  *   out      receives the plan; the plan starts unfolded (m = 1) in
  *            STENCIL_MODE_VECTOR.
  * Errors: E_ARG for a bad argument, E_UNSUPPORTED, E_NOMEM.  No device work.
@@ -272,10 +273,13 @@ int stencil_profitability(stencil_plan p, int m, int64_t *naive,
  *   periodic plans need every axis >= 2*m*r + 1 (else E_UNSUPPORTED),
  *   zero-boundary plans any axis >= 1.  T = 0 is a no-op; T < 0 is E_ARG.
  *   g->scratch, when given, must not overlap g->data.
- * Zero-boundary (STENCIL_DIRICHLET) runs copy the grid into plan-owned
- * buffers zero-padded by m*r on each face (four padded grids, kept for later
- * runs), run each application there and copy the result back; g->scratch is
- * not used and no application is fused.
+ * Dirichlet (STENCIL_DIRICHLET) runs copy the grid into plan-owned buffers
+ * padded by m*r on each face, the pad holding the ghost value (four padded
+ * grids, kept for later runs), run each application there and copy the
+ * result back; g->scratch is not used.  Plain applications of 2D FP32
+ * VECTOR plans and of 1D plans (every mode but EXACT_ORDER) fuse several per
+ * launch, the fused kernels writing the ghost value outside the grid after
+ * every step; folded applications run one per launch.
  * Enqueued asynchronously on g->stream; the caller keeps data and scratch
  * alive until that work has completed.
  * Errors: E_ARG, E_UNSUPPORTED, E_STATE, E_NOMEM, E_DEVICE.

@@ -647,13 +647,14 @@ Schedule make_schedule(stencil_plan p, const Geom &geo, int dtype, const void *d
   return sc;
 }
 
-// A zero-boundary run (reading in dirichlet.hip): the grid is copied into a
-// zero-padded buffer (pad P = m*r on the grid's axes, rows rounded up to
-// whole 256-byte lines), each application runs the periodic kernels on the
-// padded grid, then restores the zero pad; a folded application also
-// recomputes the band closer than (m-1)r to a face from m plain steps on a
-// frame of width 2(m-1)r.  Plain applications of 2D FP32 VECTOR plans fuse
-// several per launch, the fused kernel zeroing the pad at every stage.  The
+// A Dirichlet run (reading in dirichlet.hip): the grid is copied into a
+// padded buffer whose pad holds the ghost value (pad P = m*r on the grid's
+// axes, rows rounded up to whole 256-byte lines), each application runs the
+// periodic kernels on the padded grid, then restores the pad; a folded
+// application also recomputes the band closer than (m-1)r to a face from m
+// plain steps on a frame of width 2(m-1)r.  Plain applications of 2D FP32
+// VECTOR plans and of 1D plans fuse several per launch, the fused kernels
+// writing the ghost value outside the interior at every stage.  The
 // result is copied back into g->data; g->scratch is not used.
 int run_dirichlet(stencil_plan p, stencil_grid *g, int64_t T, const Geom &geo, DeviceState &d) {
   const int m = p->m, r = p->r;

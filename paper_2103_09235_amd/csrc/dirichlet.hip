@@ -20,9 +20,10 @@
 //
 // The kernels here move boxes between compact and padded arrays, run one
 // plain step on the points near the faces (a frame, or the band into the
-// application's output) and clear pads.  Each computes a point as the canonical chain (acc = +0, one FMA
-// per nonzero tap in row-major offset order); taps that read the zero pad
-// leave acc unchanged, as dropping them would.
+// application's output) and fill pads with the ghost value.  Each computes
+// a point as the canonical chain (acc = +0, one FMA per nonzero tap in
+// row-major offset order); a tap that reads the pad adds w*c in its place
+// in the chain, and with c = 0 leaves acc unchanged, as dropping it would.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

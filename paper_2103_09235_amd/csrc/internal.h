@@ -126,9 +126,10 @@ struct SweepLaunch {
   bool sym = false;    // mode SYMMETRIC: share mirrored partial sums if the operator allows
   bool sep = false;    // mode SEPARABLE: low-rank form if the operator has one
   const void *floor = nullptr;  // 1D: u = maxNum(u, floor) after every step
-  // Zero boundary on a padded 2D grid (fused 2D kernel): after every fused
-  // application the values outside rows [zbox[0], zbox[1]) x columns
-  // [zbox[2], zbox[3]) are 0, as the zero ghosts of the unpadded grid.
+  // Dirichlet boundary on a padded grid (fused 1D and 2D kernels): after
+  // every fused step the values outside rows [zbox[0], zbox[1]) x columns
+  // [zbox[2], zbox[3]) (1D: columns only) are zval, the ghosts of the
+  // unpadded grid.
   bool zb = false;
   int zbox[4] = {0, 0, 0, 0};
   double zval = 0.0;  // the ghost value the box's outside holds
