@@ -41,6 +41,7 @@
 
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -77,24 +78,24 @@ __device__ __forceinline__ void load_wrapped(const T *__restrict__ in, const T *
   }
 }
 
-// One step of a lane's VX points given the R values left and right of them.
+// One step of a lane's VX points (src, with the R values left and right of
+// them) into dst.  The step loops alternate two register arrays, two steps
+// per iteration, so no step copies its result back.
 template <typename T, int R, int VX, bool FLOOR>
-__device__ __forceinline__ void step_points(T (&cur)[VX], const T (&fl)[VX], const T (&lnb)[R],
-                                            const T (&rnb)[R], const WArr1<T, 2 * R + 1> &W) {
-  T nxt[VX];
+__device__ __forceinline__ void step_into(const T (&src)[VX], T (&dst)[VX], const T (&fl)[VX],
+                                          const T (&lnb)[R], const T (&rnb)[R],
+                                          const WArr1<T, 2 * R + 1> &W) {
 #pragma unroll
   for (int v = 0; v < VX; ++v) {
     T acc = T(0);
 #pragma unroll
     for (int o = -R; o <= R; ++o) {
       const int p = v + o;
-      const T x = p < 0 ? lnb[R + p] : (p >= VX ? rnb[p - VX] : cur[p]);
+      const T x = p < 0 ? lnb[R + p] : (p >= VX ? rnb[p - VX] : src[p]);
       acc = fma1(W.v[o + R], x, acc);
     }
-    nxt[v] = FLOOR ? max1(acc, fl[v]) : acc;
+    dst[v] = FLOOR ? max1(acc, fl[v]) : acc;
   }
-#pragma unroll
-  for (int v = 0; v < VX; ++v) cur[v] = nxt[v];
 }
 
 // Dirichlet: a lane's points (unwrapped indices first .. first+VX-1)
@@ -185,16 +186,34 @@ k_sweep1d_wave(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
   if constexpr (FLOOR) gather_span<T, VX>(floor, n, out0 - halo, lane, tile, fl);
   const int64_t first = out0 - halo + (int64_t)lane * VX;  // unwrapped
   const bool edge_span = zb && (out0 - halo < zlo || out0 - halo + 64 * VX > zhi);
-  for (int s = 0; s < k; ++s) {
-    T lnb[R], rnb[R];
+  // the step loop in two versions: spans inside the interior skip the test
+  auto steps = [&](auto masked) {
+    auto step = [&](const T (&a)[VX], T (&b)[VX]) {
+      T lnb[R], rnb[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      lnb[i] = from_left(cur[VX - R + i]);  // value at position -R + i
-      rnb[i] = from_right(cur[i]);          // value at position VX + i
+      for (int i = 0; i < R; ++i) {
+        lnb[i] = from_left(a[VX - R + i]);  // value at position -R + i
+        rnb[i] = from_right(a[i]);          // value at position VX + i
+      }
+      step_into<T, R, VX, FLOOR>(a, b, fl, lnb, rnb, W);
+      if constexpr (decltype(masked)::value) hold_ghosts<T, VX>(b, first, zlo, zhi, zval);
+    };
+    T alt[VX];
+    int s = 0;
+    for (; s + 2 <= k; s += 2) {
+      step(cur, alt);
+      step(alt, cur);
     }
-    step_points<T, R, VX, FLOOR>(cur, fl, lnb, rnb, W);
-    if (edge_span) hold_ghosts<T, VX>(cur, first, zlo, zhi, zval);
-  }
+    if (s < k) {
+      step(cur, alt);
+#pragma unroll
+      for (int v = 0; v < VX; ++v) cur[v] = alt[v];
+    }
+  };
+  if (edge_span)
+    steps(std::true_type{});
+  else
+    steps(std::false_type{});
   // back through the tile: 64 consecutive points per store instruction
 #pragma unroll
   for (int v = 0; v < VX; ++v) tile[tile_at(lane * VX + v)] = cur[v];
@@ -225,25 +244,44 @@ k_sweep1d(const T *__restrict__ in, T *__restrict__ out, int64_t n, int k,
   load_wrapped<T, VX, FLOOR>(in, floor, n, base, cur, fl);
   const bool edge_span = zb && (out0 - halo < zlo || out0 - halo + kThreads * VX > zhi);
 
-  for (int s = 0; s < k; ++s) {
-    const int b = s & 1;
+  // step s exchanges edges through buffer s & 1: a buffer is written again
+  // only after the next step's barrier, which every reader of it has passed
+  const int tl = t > 0 ? t - 1 : t;
+  const int tr = t < kThreads - 1 ? t + 1 : t;
+  // the step loop in two versions (edge_span is uniform over the block)
+  auto steps = [&](auto masked) {
+    auto step = [&](const T (&a)[VX], T (&b)[VX], int buf) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      edge[b][0][t][i] = cur[i];           // my leftmost R values
-      edge[b][1][t][i] = cur[VX - R + i];  // my rightmost R values
-    }
-    __syncthreads();
-    T lnb[R], rnb[R];
-    const int tl = t > 0 ? t - 1 : t;
-    const int tr = t < kThreads - 1 ? t + 1 : t;
+      for (int i = 0; i < R; ++i) {
+        edge[buf][0][t][i] = a[i];           // my leftmost R values
+        edge[buf][1][t][i] = a[VX - R + i];  // my rightmost R values
+      }
+      __syncthreads();
+      T lnb[R], rnb[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      lnb[i] = edge[b][1][tl][i];  // value at position -R + i
-      rnb[i] = edge[b][0][tr][i];  // value at position VX + i
+      for (int i = 0; i < R; ++i) {
+        lnb[i] = edge[buf][1][tl][i];  // value at position -R + i
+        rnb[i] = edge[buf][0][tr][i];  // value at position VX + i
+      }
+      step_into<T, R, VX, FLOOR>(a, b, fl, lnb, rnb, W);
+      if constexpr (decltype(masked)::value) hold_ghosts<T, VX>(b, base, zlo, zhi, zval);
+    };
+    T alt[VX];
+    int s = 0;
+    for (; s + 2 <= k; s += 2) {
+      step(cur, alt, 0);
+      step(alt, cur, 1);
     }
-    step_points<T, R, VX, FLOOR>(cur, fl, lnb, rnb, W);
-    if (edge_span) hold_ghosts<T, VX>(cur, base, zlo, zhi, zval);
-  }
+    if (s < k) {
+      step(cur, alt, 0);
+#pragma unroll
+      for (int v = 0; v < VX; ++v) cur[v] = alt[v];
+    }
+  };
+  if (edge_span)
+    steps(std::true_type{});
+  else
+    steps(std::false_type{});
 
 #pragma unroll
   for (int v = 0; v < VX; ++v) {
