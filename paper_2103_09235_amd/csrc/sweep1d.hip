@@ -321,13 +321,47 @@ bool use_wave_kernel(int64_t n, int R) {
   return (n + out - 1) / out <= 4 * 1024;
 }
 
+// SIMDs of the current device (4 per compute unit), queried once.
+int64_t simd_count() {
+  static const int64_t simds = [] {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1) {
+      (void)hipGetLastError();
+      return (int64_t)1024;
+    }
+    return 4 * (int64_t)cus;
+  }();
+  return simds;
+}
+
+// Points per lane of the wavefront-owned kernel: 8 while 16 would give at
+// most two wavefronts per SIMD (the steps of a lone wavefront are bound by
+// latency, so twice the wavefronts with half the points each finish sooner
+// despite the longer relative halo), else 16.  STENCIL_1D_VX = 8 or 16
+// forces one (read once per process).
+int wave_vx(int64_t n, int64_t k, int R) {
+  static const int forced = [] {
+    const char *e = std::getenv("STENCIL_1D_VX");
+    const int v = e ? std::atoi(e) : 0;
+    return (v == 8 || v == 16) ? v : 0;
+  }();
+  if (forced) return forced;
+  const int64_t out16 = kSpanWave - 2 * k * R;
+  const int64_t out8 = kSpanWave / 2 - 2 * k * R;
+  if (out8 < 1 || out16 < 1) return 16;
+  return (n + out16 - 1) / out16 <= 2 * simd_count() ? 8 : 16;
+}
+
 template <typename T, int R>
 hipError_t launch_r(const SweepLaunch &L, const std::vector<T> &w) {
   WArr1<T, 2 * R + 1> W;
   for (int i = 0; i < 2 * R + 1; ++i) W.v[i] = w[i];
   const int64_t n = L.g.nx;
   const bool wave = use_wave_kernel(n, R);
-  const int64_t span = wave ? kSpanWave : kSpanGroup;
+  const int vx = wave ? wave_vx(n, L.steps, R) : kVX;
+  const int64_t span = wave ? 64 * (int64_t)vx : kSpanGroup;
   const int64_t span_out = span - 2 * (int64_t)L.steps * R;
   if (span_out < 1) return hipErrorNotSupported;
   const int64_t spans = (n + span_out - 1) / span_out;
@@ -340,7 +374,16 @@ hipError_t launch_r(const SweepLaunch &L, const std::vector<T> &w) {
   const int64_t zlo = L.zbox[2], zhi = L.zbox[3];
   if (zb && (zlo < R || n - zhi < R || zhi <= zlo)) return hipErrorInvalidValue;
   const T zval = (T)L.zval;
-  if (wave) {
+  if (wave && vx == 8) {
+    if (fl)
+      hipLaunchKernelGGL((k_sweep1d_wave<T, R, 8, true>), dim3((unsigned)blocks), dim3(kThreads),
+                         0, L.stream, (const T *)L.in, (T *)L.out, n, L.steps, span_out, spans, W,
+                         fl, zb, zlo, zhi, zval);
+    else
+      hipLaunchKernelGGL((k_sweep1d_wave<T, R, 8, false>), dim3((unsigned)blocks),
+                         dim3(kThreads), 0, L.stream, (const T *)L.in, (T *)L.out, n, L.steps,
+                         span_out, spans, W, fl, zb, zlo, zhi, zval);
+  } else if (wave) {
     if (fl)
       hipLaunchKernelGGL((k_sweep1d_wave<T, R, kVX, true>), dim3((unsigned)blocks),
                          dim3(kThreads), 0, L.stream, (const T *)L.in, (T *)L.out, n, L.steps,
