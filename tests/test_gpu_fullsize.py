@@ -147,6 +147,9 @@ def test_heat1d_full_size_bit_exact_fp64():
     # spans per SIMD), several steps fused per launch
     ("box1d5p", 10_240_000, 60, "f64"),
     ("heat_f32", 6_000_000, 53, "f32"),
+    # a middle-length line: wavefront spans of 16 points per lane (shorter
+    # lines take 8, longer ones the workgroup spans)
+    ("heat_f64_mid", 3_000_000, 51, "f64"),
 ], ids=lambda c: c[0])
 def test_1d_long_line_sampled_bit_exact(case):
     """Sampled points of a long line, bit-exact against the oracle's sweep of
