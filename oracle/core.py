@@ -338,15 +338,28 @@ def errors(u, ref) -> dict:
     """Error of a result against the oracle, in FP64:
     e_rel  = ||u - ref||_inf / ||ref||_inf (the gate),
     e_detr = ||u - ref||_inf / ||ref - mean(ref)||_inf,
-    max_abs, and the count of bitwise-equal elements."""
+    max_abs, and the count of bitwise-equal elements (same dtype only:
+    identical bit patterns, so -0.0 differs from +0.0; 0 when the dtypes
+    differ).  A NaN anywhere in u - ref makes every norm NaN, which fails
+    any "< gate" comparison.  A zero reference norm leaves the absolute
+    error in place of the relative one."""
     u = np.asarray(u)
     ref = np.asarray(ref)
+    if u.shape != ref.shape:
+        raise ValueError("errors: shapes differ")
     d = np.abs(u.astype(np.float64) - ref.astype(np.float64))
     max_abs = float(d.max()) if d.size else 0.0
     nref = float(np.abs(ref.astype(np.float64)).max()) if d.size else 0.0
     mean = exact_sum(ref) / ref.size if ref.size else 0.0
     ndet = float(np.abs(ref.astype(np.float64) - mean).max()) if d.size else 0.0
-    same = int(np.count_nonzero(u == ref)) if u.dtype == ref.dtype else 0
+    if u.dtype == ref.dtype and u.dtype.kind == "f":
+        ui = np.ascontiguousarray(u).view(np.dtype("u%d" % u.dtype.itemsize))
+        ri = np.ascontiguousarray(ref).view(np.dtype("u%d" % ref.dtype.itemsize))
+        same = int(np.count_nonzero(ui == ri))
+    elif u.dtype == ref.dtype:
+        same = int(np.count_nonzero(u == ref))
+    else:
+        same = 0
     return {
         "e_rel": max_abs / nref if nref > 0 else max_abs,
         "e_detr": max_abs / ndet if ndet > 0 else max_abs,

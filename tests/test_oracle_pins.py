@@ -742,3 +742,181 @@ def test_floor_sweep_rational_brute_force():
     got = oracle.floor_sweep(np.array([float(v) for v in w]), np.array([float(v) for v in u]),
                              np.array([float(v) for v in fl]), 4)
     assert np.max(np.abs(got - np.array([float(v) for v in ref]))) < 16 * EPS64
+
+
+# ------------------------------------------- error metrics (the parity gate)
+
+def _errors_expected_case():
+    """Hand-computed metrics: ref = (2, -4, 2, 12) has max |ref| = 12 and
+    exact mean 3, so max |ref - mean| = 9; u = (2, -6, 2, 15) differs by 2 at
+    the second element and by 3 at the last, so max_abs = 3,
+    e_rel = 3 / 12 = 0.25 and e_detr = 3 / 9; two elements are bitwise
+    equal."""
+    ref = np.array([2.0, -4.0, 2.0, 12.0])
+    u = np.array([2.0, -6.0, 2.0, 15.0])
+    return u, ref, {"e_rel": 0.25, "e_detr": 3.0 / 9.0, "max_abs": 3.0, "bit_equal": 2, "n": 4}
+
+
+def test_errors_hand_computed():
+    u, ref, want = _errors_expected_case()
+    assert oracle.errors(u, ref) == want
+    # the same values in 2D and in FP32 (all dyadic, exact in both)
+    got32 = oracle.errors(u.astype(np.float32).reshape(2, 2), ref.astype(np.float32).reshape(2, 2))
+    assert got32 == want
+    # mixed dtypes: the norms hold, no element counts as bitwise equal
+    mixed = oracle.errors(u.astype(np.float32), ref)
+    assert mixed["e_rel"] == 0.25 and mixed["bit_equal"] == 0
+
+
+def test_errors_special_cases():
+    # identical arrays: zero error, every element bitwise equal
+    a = synth.grid_f32((7, 5))
+    e = oracle.errors(a, a.copy())
+    assert e["e_rel"] == 0.0 and e["e_detr"] == 0.0 and e["max_abs"] == 0.0
+    assert e["bit_equal"] == 35
+    # -0.0 against +0.0: numerically equal, not bitwise equal
+    z = oracle.errors(np.array([-0.0, 1.0]), np.array([0.0, 1.0]))
+    assert z["max_abs"] == 0.0 and z["bit_equal"] == 1
+    # a constant reference: detrended norm 0, so e_detr falls back to max_abs
+    c = oracle.errors(np.array([2.0, 2.25, 2.0]), np.array([2.0, 2.0, 2.0]))
+    assert c["e_rel"] == 0.125 and c["e_detr"] == 0.25
+    # a zero reference: e_rel is the absolute error
+    zr = oracle.errors(np.array([0.5, 0.0]), np.zeros(2))
+    assert zr["e_rel"] == 0.5
+    # a NaN anywhere must fail every gate
+    n = oracle.errors(np.array([1.0, np.nan]), np.array([1.0, 1.0]))
+    assert not (n["e_rel"] < 1e-5)
+    with pytest.raises(ValueError):
+        oracle.errors(np.zeros(3), np.zeros(4))
+
+
+def test_errors_pin_catches_wrong_norms():
+    """Plausible mistakes in the metric (normalising by u instead of ref, a
+    2-norm, per-element relative error, the mean of u, a metric that
+    returns 0, a value-equality count) each give a different value on the
+    hand-computed case, so the pin above would catch them."""
+    u, ref, want = _errors_expected_case()
+    d = np.abs(u - ref)
+    mutants = {
+        "norm of u": d.max() / np.abs(u).max(),
+        "2-norm": np.linalg.norm(d) / np.linalg.norm(ref),
+        "elementwise relative": (d / np.abs(ref)).max(),
+        "zero": 0.0,
+    }
+    for name, val in mutants.items():
+        assert val != want["e_rel"], name
+    assert d.max() / np.abs(u - u.mean()).max() != want["e_detr"]
+    assert d.max() / np.abs(ref - np.median(ref)).max() != want["e_detr"]
+    assert int(np.count_nonzero(np.array([-0.0]) == np.array([0.0]))) == 1  # value equality would count it
+
+
+# -------------------------------------- FP32 mirror of a folded run (reading 3)
+
+@pytest.mark.parametrize("dim,m,T,shape", [
+    (1, 3, 7, (19,)), (2, 2, 5, (9, 11)), (2, 3, 7, (10, 12)), (2, 4, 6, (13, 9)), (3, 2, 3, (5, 6, 7)),
+])
+def test_folded_reference_f32_exact_on_integer_data(dim, m, T, shape):
+    """Integer weights and inputs with every intermediate value below 2^24:
+    every FP32 operation is exact, so the mirror of floor(T/m) folded sweeps
+    and T mod m plain ones must equal the exact rational brute force of T
+    plain steps (T not divisible by m, so the remainder is exercised), and
+    the FP64 oracle."""
+    g = rng(100 + dim * 10 + m)
+    w = g.integers(0, 2, size=(3,) * dim).astype(np.int64)
+    w[(1,) * dim] = 1
+    u0 = g.integers(0, 3, size=shape).astype(np.int64)
+    assert int(np.abs(w).sum()) ** T * 2 < 2 ** 24
+    ref = brute_force(w.astype(object), u0.astype(object), T).astype(np.float64)
+    got = oracle.folded_reference_f32(w.astype(np.float64), u0.astype(np.float32), T, m)
+    assert got.dtype == np.float32
+    assert np.array_equal(got.astype(np.float64), ref)
+    assert np.array_equal(got.astype(np.float64), oracle.sweep(w.astype(np.float64), u0.astype(np.float64), T))
+
+
+def test_folded_reference_f32_m1_is_the_plain_mirror():
+    w = synth.WORKLOADS["box2d"].weights
+    u0 = synth.grid_f32((12, 17))
+    got = oracle.folded_reference_f32(w, u0, 9, 1)
+    # exact FP32 chain: pinned separately against a per-tap rational FMA chain
+    assert np.array_equal(got, oracle.sweep_f32(w.astype(np.float32), u0, 9))
+
+
+@pytest.mark.parametrize("name,m,T", [("star2d", 2, 41), ("star2d", 4, 42), ("box2d", 4, 30),
+                                       ("box2d", 8, 35), ("heat1d", 5, 23), ("box3d", 2, 7)])
+def test_folded_reference_f32_within_derived_bound(name, m, T):
+    """Against the FP64 oracle on the same (FP32-exact) weights.  Positive
+    weights summing to 1 give ||W||_1 = 1 for every fold, so errors do not
+    grow from sweep to sweep.  Per folded sweep: each weight rounded to FP32
+    (|dW| <= u |W|), the mass-compensated centre off by at most the other
+    weights' rounding plus its own (<= 2u ||W||_1 in all), and a chain of
+    n = |S_m| FMAs with error <= gamma_n = n u / (1 - n u) times
+    sum |W| |v| <= ||v||_inf; per plain sweep gamma_|S| + u.  With
+    u = 2^-24 the absolute error after q folded and s plain sweeps is at most
+    (q (gamma_|S_m| + 3u) + s (gamma_|S| + u)) (1 + 3u)^(q+s) ||u0||_inf."""
+    wl = synth.WORKLOADS[name]
+    w = synth.to_f32_exact(wl.weights)
+    dim = w.ndim
+    shape = {1: (61,), 2: (23, 29), 3: (9, 10, 11)}[dim]
+    u0 = synth.grid_f32(shape)
+    got = oracle.folded_reference_f32(w, u0, T, m)
+    ref = oracle.sweep(w, u0.astype(np.float64), T)
+    q, s = oracle.schedule(T, m)
+    u = 2.0 ** -24
+    nS = int(np.count_nonzero(w))
+    nSm = int(np.count_nonzero(oracle.fold_weights(w, m)))
+    gamma = lambda n: n * u / (1 - n * u)  # noqa: E731
+    bound = (q * (gamma(nSm) + 3 * u) + s * (gamma(nS) + u)) * (1 + 3 * u) ** (q + s) * float(np.abs(u0).max())
+    err = oracle.errors(got, ref)["max_abs"]
+    assert 0 < err <= bound
+    # a dropped remainder (floor(T/m) folded sweeps only) breaks the bound
+    if s:
+        short = oracle.sweep_f32(oracle.fold_weights_f32(w, m), u0, q)
+        assert oracle.errors(short, ref)["max_abs"] > bound
+
+
+# ------------------------------------------------- FP32 branch of the floor sweep
+
+def test_floor_sweep_f32_exact_on_dyadic_data():
+    """Dyadic weights (1/4, 1/2, 1/4) and inputs on a grid of 2^-4 keep every
+    FP32 step exact for T steps (numerators below 2^(4 + 2T) < 2^24), so the
+    FP32 branch must equal the exact rational brute force of
+    u <- max(A u, floor), and the FP64 branch."""
+    n, T = 17, 8
+    g = rng(21)
+    u = [Fraction(int(v), 16) for v in g.integers(0, 16, size=n)]
+    fl = [Fraction(int(v), 16) for v in g.integers(0, 10, size=n)]
+    w = [Fraction(1, 4), Fraction(1, 2), Fraction(1, 4)]
+    ref = list(u)
+    for _ in range(T):
+        ref = [max(sum(w[o + 1] * ref[(i + o) % n] for o in (-1, 0, 1)), fl[i]) for i in range(n)]
+    wf = np.array([0.25, 0.5, 0.25])
+    u32 = np.array([float(v) for v in u], dtype=np.float32)
+    fl32 = np.array([float(v) for v in fl], dtype=np.float32)
+    got = oracle.floor_sweep(wf, u32, fl32, T, f32=True)
+    assert got.dtype == np.float32
+    assert np.array_equal(got.astype(np.float64), np.array([float(v) for v in ref]))
+    assert np.array_equal(got.astype(np.float64),
+                          oracle.floor_sweep(wf, u32.astype(np.float64), fl32.astype(np.float64), T))
+    # the floor taken before the stencil instead of after it gives another result
+    wrong = u32.copy()
+    for _ in range(T):
+        wrong = oracle.sweep_f32(wf.astype(np.float32), np.fmax(wrong, fl32), 1)
+    assert not np.array_equal(wrong, got)
+
+
+def test_floor_sweep_f32_close_to_fp64():
+    """Non-dyadic weights (the APOP discount): each FP32 step adds at most
+    (gamma_3 + u) ||v||_inf of error before the max, and max(., floor) is
+    1-Lipschitz, so after T steps |u32 - u64| <= T (gamma_3 + u) ||u0||_inf
+    plus the floor's own rounding (u ||floor||_inf)."""
+    w = synth.to_f32_exact(synth.APOP["weights"])
+    n, T = 200, 60
+    u0 = synth.apop_payoff(n).astype(np.float32)
+    fl = u0.copy()
+    got = oracle.floor_sweep(w, u0, fl, T, f32=True)
+    ref = oracle.floor_sweep(w, u0.astype(np.float64), fl.astype(np.float64), T)
+    u = 2.0 ** -24
+    bound = (T * (3 * u / (1 - 3 * u) + u) + u) * float(np.abs(u0).max())
+    err = oracle.errors(got, ref)["max_abs"]
+    assert err <= bound
+    assert np.all(got >= fl)
