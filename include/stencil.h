@@ -317,7 +317,9 @@ int stencil_run_schedule(stencil_plan p, const stencil_grid *g, int64_t T,
  * fold depth is not changed.  Results equal the plain canonical-order sweep
  * of the chosen operators bit for bit.  opts may be NULL (no tuning, no
  * graph, m = 1).  The library keeps device tables (and the graph) of the last
- * four batches, keyed by every argument.
+ * four batches, keyed by every argument (each plan by an id that no other
+ * plan of the process ever takes, not by its address); destroying a plan
+ * frees the cached batches that name it.
  * Errors: E_ARG, E_UNSUPPORTED, E_NOMEM, E_DEVICE.
  */
 int stencil_run_batched(const stencil_plan *plans, stencil_grid *grids,
@@ -336,8 +338,9 @@ int stencil_residual(const void *u, const void *ref, int dtype, int64_t n,
                      void *stream, double *out);
 
 /* stencil_plan_destroy -- free the plan and everything it owns (weights,
- * cached scratch, graphs).  NULL is ignored.  The caller must ensure no work
- * using the plan is still in flight. */
+ * cached scratch, graphs, and the cached batched runs that name it).  NULL is
+ * ignored.  The caller must ensure no work using the plan is still in
+ * flight. */
 void stencil_plan_destroy(stencil_plan p);
 
 /* stencil_last_error -- thread-local description of the last failure on

@@ -759,6 +759,21 @@ int tune_batched(stencil_plan p, int side, int max_m, int64_t T, hipStream_t str
 
 }  // namespace
 
+void evict_batched_plan(const stencil_plan_s *p) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (auto it = g_cache.begin(); it != g_cache.end();) {
+    bool names = false;
+    // words 4 + 6 i hold the plans' ids
+    for (size_t k = 4; k < it->key.size() && !names; k += 6) names = it->key[k] == p->id;
+    if (names) {
+      free_entry(*it);
+      it = g_cache.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
 }  // namespace stencil
 
 using namespace stencil;
@@ -837,7 +852,7 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
   key.push_back(use_graph ? 1 : 0);
   key.push_back((uint64_t)(uintptr_t)stream);
   for (int i = 0; i < count; ++i) {
-    key.push_back((uint64_t)(uintptr_t)plans[i]);
+    key.push_back(plans[i]->id);  // never reused, unlike the plan's address
     key.push_back((uint64_t)(uintptr_t)grids[i].data);
     key.push_back((uint64_t)(uintptr_t)grids[i].scratch);
     key.push_back((uint64_t)grids[i].shape[0]);

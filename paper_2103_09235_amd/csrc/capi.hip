@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -273,6 +275,8 @@ int stencil_plan_create(int dim, int radius, int shape, const double *weights,
   }
   stencil_plan p = new (std::nothrow) stencil_plan_s();
   if (!p) return fail(STENCIL_E_NOMEM, "plan allocation failed");
+  static std::atomic<uint64_t> next_id{1};
+  p->id = next_id.fetch_add(1);
   try {
     p->dim = dim;
     p->r = radius;
@@ -548,6 +552,15 @@ int check_run(stencil_plan p, const stencil_grid *g, int64_t T, Geom &geo) {
       return fail(STENCIL_E_UNSUPPORTED,
                   "every grid axis must be >= 2*m*r+1 for this plan");
   if (geo.count() > ((int64_t)1 << 40)) return fail(STENCIL_E_UNSUPPORTED, "grid too large");
+  if (p->boundary == STENCIL_DIRICHLET) {
+    // the fused kernels take the padded grid's interior box (each axis
+    // padded by m*r on both sides, rows rounded up to 256 bytes) as int
+    const int64_t lim = (int64_t)INT_MAX - 2 * (int64_t)p->m * p->r - 64;
+    for (int a = 0; a < p->dim; ++a)
+      if (g->shape[a] > lim)
+        return fail(STENCIL_E_UNSUPPORTED,
+                    "zero-boundary grid axes must be below 2^31 - 2*m*r - 64 points");
+  }
   if (p->floor) {
     if (p->m != 1)
       return fail(STENCIL_E_UNSUPPORTED, "a floor makes the update nonlinear: fold depth must be 1");
@@ -892,6 +905,7 @@ int stencil_residual(const void *u, const void *ref, int dtype, int64_t n,
 
 void stencil_plan_destroy(stencil_plan p) {
   if (!p) return;
+  evict_batched_plan(p);
   free_plan_devices(p);
   delete p;
 }

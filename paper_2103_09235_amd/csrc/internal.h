@@ -73,6 +73,7 @@ struct DeviceState {
 }  // namespace stencil
 
 struct stencil_plan_s {
+  uint64_t id = 0;            // unique per plan created in this process (never reused)
   int dim = 0, r = 0, shape = 0, boundary = 0, mode = STENCIL_MODE_VECTOR;
   int max_fuse = 0;           // steps one launch may fuse; 0 = library choice
   double bvalue = 0.0;        // Dirichlet ghost value
@@ -95,6 +96,8 @@ namespace stencil {
 void free_plan_devices(stencil_plan_s *p);
 // Drop the captured run graphs of a plan (all devices).
 void drop_plan_graphs(stencil_plan_s *p);
+// Free every cached batched run that names the plan (batched.hip).
+void evict_batched_plan(const stencil_plan_s *p);
 
 int side_of(int R);
 int64_t count_of(int dim, int R);

@@ -250,6 +250,28 @@ def test_run_schedule_counts_launches():
     assert e.value.code == sf.STENCIL_E_UNSUPPORTED
 
 
+def test_dirichlet_rejects_axes_beyond_int_range():
+    """The fused zero-boundary kernels index the padded grid's interior box
+    with 32-bit integers: axes whose padded extent would pass 2^31 are
+    refused before any device work (a 1D line of 2^32 + 5 points would
+    otherwise wrap to a 5-point interior)."""
+    heat = sf.Plan(synth.heat1d_weights(), sf.STENCIL_STAR, sf.STENCIL_DIRICHLET)
+    for n in ((1 << 32) + 5, (1 << 31) - 1):
+        with pytest.raises(sf.StencilError) as e:
+            _sched(heat, (n,), 10, sf.STENCIL_F64)
+        assert e.value.code == sf.STENCIL_E_UNSUPPORTED
+        assert "zero-boundary" in str(e.value)
+    assert _sched(heat, ((1 << 31) - 67,), 10, sf.STENCIL_F64)["plain_launches"] >= 1
+    # radius 2: the limit moves down by the wider pad
+    box5 = sf.Plan(synth.WORKLOADS["box1d5p"].weights, sf.STENCIL_BOX, sf.STENCIL_DIRICHLET)
+    with pytest.raises(sf.StencilError):
+        _sched(box5, ((1 << 31) - 68,), 10, sf.STENCIL_F64)
+    assert _sched(box5, ((1 << 31) - 69,), 10, sf.STENCIL_F64)["plain_launches"] >= 1
+    # periodic lines of that length stay legal
+    per = sf.Plan(synth.heat1d_weights(), sf.STENCIL_STAR)
+    assert _sched(per, ((1 << 32) + 5,), 10, sf.STENCIL_F64)["plain_launches"] >= 1
+
+
 def test_separable_rank_and_mode():
     """Rank of the operator by complete-pivoting elimination (host only) and
     when the separable form applies (rank 1 or 2, fewer FMAs than taps)."""

@@ -321,6 +321,30 @@ def test_batched_autotune_picks_valid_m(tmp_path):
         assert np.array_equal(o, oracle.folded_reference_f32(w, g, T, m))
 
 
+def test_batched_cache_never_confuses_plans():
+    """Plans destroyed and created between batched runs on the same tensors
+    (a new plan may sit at a freed plan's address): every run must apply its
+    own plan's operator, including a plan of the same kind and radius with
+    other weights, whose cached tables would otherwise be reused."""
+    sides = [96, 130, 64, 300]
+    grids0 = [synth.grid_f32((s, s), stream=9 + i) for i, s in enumerate(sides)]
+    datas = [torch.from_numpy(g).to(DEV) for g in grids0]
+    scr = [torch.empty_like(d) for d in datas]
+    T = 5
+    for it in range(6):
+        kind = synth.STAR if it % 3 != 2 else synth.BOX
+        mask = synth.star_mask(2, 1) if kind == synth.STAR else None
+        w = synth.to_f32_exact(synth.random_positive_weights(2, 1, offset=100 + 9 * it, mask=mask))
+        plan = sf.Plan(w, sf.STENCIL_STAR if kind == synth.STAR else sf.STENCIL_BOX)
+        for d, g in zip(datas, grids0):
+            d.copy_(torch.from_numpy(g))
+        sf.stencil_run_batched([plan.handle] * len(datas), datas, scr, T, use_graph=it % 2 == 0)
+        torch.cuda.synchronize()
+        for d, g in zip(datas, grids0):
+            assert np.array_equal(d.cpu().numpy(), oracle.folded_reference_f32(w, g, T, 1)), it
+        plan.close()
+
+
 # ------------------------------------------- shared-partial-sum (symmetric)
 
 def _symmetric_box():
