@@ -68,6 +68,9 @@ def run(w, kind, u0, T, m, mode=sf.STENCIL_MODE_VECTOR):
     ("box2d", 4, 8, "vector"), ("box2d", 8, 8, "vector"), ("box2d", 4, 8, "mfma"),
     ("box2d", 8, 16, "mfma"), ("star3d", 2, 4, "vector"), ("box3d", 2, 4, "vector"),
     ("box3d", 1, 3, "vector"), ("unitbox2d", 8, 16, "separable"), ("box2d", 1, 16, "vector"),
+    # the headline launch geometry: two fused launches of 12 steps each
+    # (strip height from the occupancy query), and the plain 7-point 3D star
+    ("star2d", 1, 24, "vector"), ("star3d", 1, 3, "vector"),
 ])
 def test_sampled_outputs_full_size(name, m, T, mode):
     wl = synth.WORKLOADS[name]
@@ -88,6 +91,11 @@ def test_sampled_outputs_full_size(name, m, T, mode):
                       for p in pts])
     err = np.max(np.abs(got - ref64)) / np.max(np.abs(ref64))
     assert err < (1e-3 if mode == "mfma" else 1e-5), err
+    if (name, m, T) == ("star2d", 1, 24):
+        plan = sf.Plan(wl.weights, wl.shape_kind)
+        sched = sf.stencil_run_schedule(plan.handle, wl.shape, sf.STENCIL_F32, T, 1 << 30, 1 << 34)
+        assert (sched["plain_launches"], sched["final_copy"]) == (2, False)
+        plan.close()
     if mode == "separable":
         plan = sf.Plan(wl.weights, wl.shape_kind)
         plan.fold(m)
