@@ -13,6 +13,7 @@ from .core import (  # noqa: F401
     sweep,
     sweep_f32,
     sweep_window,
+    sweep_spectral,
     fold_weights,
     fold_weights_f32,
     bf16_rne,

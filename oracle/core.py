@@ -149,6 +149,125 @@ def sweep_window(w, u0, T: int, points, f32: bool = False) -> np.ndarray:
     return np.array(vals, dtype=np.float32 if f32 else np.float64)
 
 
+def _cpow(z: np.ndarray, T: int) -> np.ndarray:
+    """z**T for an integer T >= 0 by binary exponentiation (about 2 log2 T
+    complex products, each rounded once per component)."""
+    out = np.ones_like(z)
+    base = z.copy()
+    e = int(T)
+    while e:
+        if e & 1:
+            out *= base
+        e >>= 1
+        if e:
+            base *= base
+    return out
+
+
+def sweep_spectral(w, u0, T: int, boundary: str = "periodic", workers: int | None = None) -> np.ndarray:
+    """u_T = A^T u_0 in FP64 through the eigen-decomposition of A, for grids
+    too large for the naive loop (Section 1's sweep; the same operator as
+    ``sweep``, evaluated in another order).
+
+    periodic: A is circulant (correlation with w, every axis wrapped), so the
+    discrete Fourier transform diagonalises it: with
+    u_hat(k) = sum_x u[x] e^{-2 pi i k.x/n}, (A u)_hat(k) = lambda(k) u_hat(k)
+    where lambda(k) = sum_o w[o] e^{+2 pi i k.o/n}; hence
+    u_T = IDFT(DFT(u_0) lambda^T).  Offsets that alias on short axes add up,
+    as in the circulant matrix.
+
+    zero (Dirichlet ghosts 0; radius 1, weights unchanged by reversing any
+    axis): A is a sum of Kronecker products of I and the truncated
+    nearest-neighbour operator J (ones next to the diagonal), both diagonalised
+    by the type-I discrete sine transform, J having the eigenvalues
+    2 cos(pi j/(n+1)), j = 1..n; so lambda(j) = sum_o w[o] prod_a c(o_a, j_a)
+    with c(0, j) = 1 and c(+-1, j) = cos(pi j/(n+1)) (each of the two
+    mirrored taps takes one half of J's eigenvalue).
+
+    Rounding: one forward and one inverse transform (error of order
+    eps log2 N relative to ||u_0||) and lambda^T by binary powering
+    (about 2 log2 T roundings); far below the FP32 and BF16 tolerances it
+    is used for, but not bit-exact (the naive loop is the bit-exact one)."""
+    import scipy.fft as sfft
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    dim = u0.ndim
+    r = _radius_of(w, dim)
+    if T < 0:
+        raise ValueError("T >= 0")
+    workers = workers or os.cpu_count() or 1
+    shape = u0.shape
+    if boundary == "periodic":
+        # per axis: phases e^{2 pi i k o / n} for o in [-r, r] over the axis's
+        # transform frequencies (the last axis: the n//2+1 of the real DFT),
+        # angle from (k*o mod n) so each is rounded once
+        phases = []
+        for a, n in enumerate(shape):
+            k = np.arange(n // 2 + 1 if a == dim - 1 else n, dtype=np.int64)
+            rows = []
+            for o in range(-r, r + 1):
+                rows.append(np.exp(2j * np.pi * ((k * o) % n) / n))
+            phases.append(rows)
+        lam = None
+        for idx in np.ndindex(*w.shape):
+            wo = w[idx]
+            if wo == 0.0:
+                continue
+            term = None
+            for a in range(dim):
+                v = phases[a][idx[a]]
+                sh = [1] * dim
+                sh[a] = v.size
+                v = v.reshape(sh)
+                term = v if term is None else term * v
+            term = wo * term
+            lam = term if lam is None else lam + term
+        if lam is None:
+            return np.zeros_like(u0) if T > 0 else u0.copy()
+        lam = np.broadcast_to(lam, tuple(shape[:-1]) + (shape[-1] // 2 + 1,))
+        uh = sfft.rfftn(u0, workers=workers)
+        uh *= _cpow(np.ascontiguousarray(lam), T)
+        return sfft.irfftn(uh, s=shape, workers=workers)
+    if boundary == "zero":
+        if r != 1:
+            raise ValueError("the sine-transform form needs radius 1")
+        for a in range(dim):
+            if not np.array_equal(w, np.flip(w, axis=a)):
+                raise ValueError("the sine-transform form needs weights symmetric in every axis")
+        lam = np.zeros((1,) * dim)
+        for idx in np.ndindex(*w.shape):
+            wo = w[idx]
+            if wo == 0.0:
+                continue
+            term = np.ones((1,) * dim)
+            for a, n in enumerate(shape):
+                sh = [1] * dim
+                sh[a] = n
+                if idx[a] != 1:
+                    c = np.cos(np.pi * np.arange(1, n + 1) / (n + 1)).reshape(sh)
+                    term = term * c
+            lam = lam + wo * term
+        lam = np.broadcast_to(lam, shape)
+        uh = sfft.dstn(u0, type=1, norm="ortho", workers=workers)
+        uh *= _rpow(np.ascontiguousarray(lam), T)
+        return sfft.dstn(uh, type=1, norm="ortho", workers=workers)
+    raise ValueError("boundary must be periodic or zero")
+
+
+def _rpow(x: np.ndarray, T: int) -> np.ndarray:
+    """x**T (real) by binary exponentiation."""
+    out = np.ones_like(x)
+    base = x.copy()
+    e = int(T)
+    while e:
+        if e & 1:
+            out *= base
+        e >>= 1
+        if e:
+            base *= base
+    return out
+
+
 def fold_weights(w, m: int) -> np.ndarray:
     """Folded weights W_m of m steps (Section 3.1 and Section 3.3: the m-step
     expansion with merged terms and reassigned weights, the "folding matrix";

@@ -920,3 +920,76 @@ def test_floor_sweep_f32_close_to_fp64():
     err = oracle.errors(got, ref)["max_abs"]
     assert err <= bound
     assert np.all(got >= fl)
+
+
+# ------------------------------------- spectral form (full-size error reference)
+
+@pytest.mark.parametrize("shape,r", [((1,), 1), ((2,), 1), ((5,), 2), ((7,), 1), ((3, 5), 1),
+                                     ((4, 3), 2), ((2, 3, 4), 1)])
+def test_spectral_against_rational_brute_force(shape, r):
+    """Random real weights (asymmetric, so the orientation matters) on tiny
+    grids, including sides shorter than 2r+1 where offsets alias: the
+    spectral form agrees with the exact rational value of A^T u0 to a few
+    ulps of the data's scale."""
+    dim = len(shape)
+    g = rng(hash((shape, r, "spec")) % 2**32)
+    w = g.random((2 * r + 1,) * dim)
+    w /= w.sum()
+    u0 = g.random(shape)
+    T = 5
+    ref = brute_force(exact(w), exact(u0), T)
+    got = oracle.sweep_spectral(w, u0, T)
+    err = max(abs(Fraction(float(a)) - b) for a, b in zip(got.ravel(), ref.ravel()))
+    assert float(err) <= 64 * EPS64 * float(np.abs(u0).max())
+
+
+@pytest.mark.parametrize("name,shape,T", [("heat1d", (1000,), 100), ("star2d", (96, 130), 250),
+                                          ("box2d", (64, 96), 100), ("star3d", (20, 24, 28), 40),
+                                          ("box3d", (16, 18, 20), 30)])
+def test_spectral_against_naive_sweep(name, shape, T):
+    """The naive loop (pinned above by brute force) and the spectral form
+    agree to the FFT's rounding on the workloads' own stencils, the random
+    2D box being asymmetric."""
+    w = synth.to_f32_exact(synth.WORKLOADS[name].weights)
+    u0 = synth.grid_f64(shape)
+    a = oracle.sweep(w, u0, T)
+    b = oracle.sweep_spectral(w, u0, T)
+    assert np.max(np.abs(a - b)) <= 1e-13 * float(np.abs(u0).max())
+
+
+def test_spectral_fourier_mode_and_planted_conjugate():
+    """A single Fourier mode decays by |lambda(k)|^T and turns by T arg
+    lambda(k) (the closed form); conjugating lambda (the flipped
+    orientation u[x-o]) misses it for the asymmetric random box."""
+    w = synth.WORKLOADS["box2d"].weights
+    for k, T in (((5, 7), 9), ((1, 2), 4), ((2, 1), 30)):
+        u0, want, _ = fourier_closed_form(w, (24, 30), k, T)
+        scale = float(np.abs(want).max())
+        got = oracle.sweep_spectral(w, u0, T)
+        assert np.max(np.abs(got - want)) < 1e-13
+        flipped = oracle.sweep_spectral(w[::-1, ::-1].copy(), u0, T)
+        assert np.max(np.abs(flipped - want)) > 1e-2 * scale
+
+
+def test_spectral_zero_boundary():
+    """Zero ghosts through the sine transform: equal to the naive zero-ghost
+    loop (pinned by brute force with dropped taps), and a sine mode decays by
+    its closed-form eigenvalue; asymmetric or wider stencils are refused."""
+    w = synth.star2d_weights(0.6, 0.1)
+    u0 = synth.grid_f64((30, 41))
+    for T in (1, 6, 57):
+        a = oracle.sweep(w, u0, T, "zero")
+        b = oracle.sweep_spectral(w, u0, T, "zero")
+        assert np.max(np.abs(a - b)) <= 1e-13
+    box = np.array([[0.05, 0.1, 0.05], [0.1, 0.4, 0.1], [0.05, 0.1, 0.05]])
+    assert np.max(np.abs(oracle.sweep(box, u0, 8, "zero") - oracle.sweep_spectral(box, u0, 8, "zero"))) < 1e-13
+    n, kk, T = 31, 4, 12
+    x = np.arange(1, n + 1)
+    mode = np.sin(np.pi * kk * x / (n + 1))
+    lam = 0.5 + 0.5 * np.cos(np.pi * kk / (n + 1))
+    got = oracle.sweep_spectral(np.array([0.25, 0.5, 0.25]), mode, T, "zero")
+    assert np.max(np.abs(got - lam ** T * mode)) < 1e-14
+    with pytest.raises(ValueError):
+        oracle.sweep_spectral(synth.WORKLOADS["box2d"].weights, u0, 2, "zero")
+    with pytest.raises(ValueError):
+        oracle.sweep_spectral(np.ones((5, 5)) / 25, u0, 2, "zero")
