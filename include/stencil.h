@@ -337,6 +337,28 @@ int stencil_run_batched(const stencil_plan *plans, stencil_grid *grids,
 int stencil_residual(const void *u, const void *ref, int dtype, int64_t n,
                      void *stream, double *out);
 
+/*
+ * stencil_residual_noalloc -- the reductions of stencil_residual, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): no hipMalloc, hipFree or
+ * allocating library call, no host synchronisation.
+ *   u, ref, dtype, n  as for stencil_residual (ref nullable).
+ *   stream            hipStream_t or NULL; the work is enqueued there.
+ *   out_dev           device, caller-owned, 3 doubles: receives sum u,
+ *                     sum |u - ref|, max |u - ref| when the stream reaches
+ *                     the work (n = 0 gives 0, 0, 0).
+ * The 512 per-block partial sums live in a fixed per-device array of the
+ * library (32 KiB, held until the process ends); every call on a GPU reuses
+ * that GPU's array, so calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  The array's address
+ * is looked up on the first call on each device.  The reduction tree is the
+ * one stencil_residual uses, so the results are bit-identical to it.
+ * Errors: E_ARG, E_UNSUPPORTED (partials larger than the array: never with
+ * this build's constants), E_DEVICE.
+ */
+int stencil_residual_noalloc(const void *u, const void *ref, int dtype, int64_t n,
+                             void *stream, double *out_dev);
+
 /* stencil_plan_destroy -- free the plan and everything it owns (weights,
  * cached scratch, graphs, and the cached batched runs that name it).  NULL is
  * ignored.  The caller must ensure no work using the plan is still in

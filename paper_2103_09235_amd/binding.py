@@ -37,6 +37,7 @@ EXPORTS = (
     "stencil_plan_set_floor", "stencil_life", "stencil_life_launches",
     "stencil_plan_info",
     "stencil_profitability", "stencil_run", "stencil_run_schedule", "stencil_run_batched", "stencil_residual",
+    "stencil_residual_noalloc",
     "stencil_plan_destroy", "stencil_last_error", "stencil_version",
 )
 
@@ -105,6 +106,7 @@ def _load() -> ctypes.CDLL:
                                         ctypes.c_int, ctypes.c_int64,
                                         ctypes.POINTER(stencil_batch_opts)]
     lib.stencil_residual.argtypes = [P, P, ctypes.c_int, ctypes.c_int64, P, dp]
+    lib.stencil_residual_noalloc.argtypes = [P, P, ctypes.c_int, ctypes.c_int64, P, P]
     lib.stencil_plan_destroy.argtypes = [P]
     lib.stencil_plan_destroy.restype = None
     lib.stencil_last_error.restype = ctypes.c_char_p
@@ -334,6 +336,21 @@ def stencil_residual(u, ref=None, stream=None):
     _check(lib.stencil_residual(u.data_ptr(), ref.data_ptr() if ref is not None else None,
                                 _dtype_code(u), u.numel(), s, out))
     return out[0], out[1], out[2]
+
+
+def stencil_residual_noalloc(u, out, ref=None, stream=None) -> None:
+    """Enqueue (sum u, sum |u - ref|, max |u - ref|) into the device tensor
+    out (3 float64) without any allocation by the library."""
+    import torch
+    if ref is not None and (ref.shape != u.shape or ref.dtype != u.dtype):
+        raise StencilError(STENCIL_E_ARG, "ref must match u")
+    if out.dtype != torch.float64 or out.numel() < 3 or not out.is_contiguous():
+        raise StencilError(STENCIL_E_ARG, "out must be a contiguous float64 tensor of 3 values")
+    if stream is None:
+        stream = torch.cuda.current_stream(u.device)
+    s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(lib.stencil_residual_noalloc(u.data_ptr(), ref.data_ptr() if ref is not None else None,
+                                        _dtype_code(u), u.numel(), s, out.data_ptr()))
 
 
 def stencil_plan_destroy(plan) -> None:

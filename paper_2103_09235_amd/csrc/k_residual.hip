@@ -4,6 +4,9 @@
 // pairing order), so results are bit-reproducible run to run.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include "internal.h"
 
 namespace stencil {
@@ -107,3 +110,68 @@ hipError_t launch_residual(const void *u, const void *ref, int dtype, int64_t n,
 }
 
 }  // namespace stencil
+
+// ------------------------------------------------ allocation-free variant
+//
+// The partial sums of stencil_residual_noalloc live in a fixed device array
+// instead of a per-call allocation.  Host code never passes the array's name
+// to a kernel (on the host it is only a stand-in for the symbol): its device
+// address is looked up once per device with hipGetSymbolAddress and that
+// address is what the kernels receive.
+namespace {
+
+constexpr int kResidualBlocks = 512;   // same reduction tree as stencil_residual
+constexpr size_t kScratchDoubles = 4096;  // 32 KiB per device
+constexpr size_t kScratchNeed = (size_t)kResidualBlocks * 5;  // per-block partials
+static_assert(kScratchNeed <= kScratchDoubles, "residual partials exceed the scratch array");
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_ptr;  // device ordinal -> address of scratch
+
+// The device address of scratch on the current device (looked up on the
+// first call there).
+int scratch_on_current_device(double **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return stencil::hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return STENCIL_OK;
+  }
+  double *ptr = nullptr;
+  e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return stencil::hip_fail(e, "hipGetSymbolAddress(scratch)");
+  if (!ptr) return stencil::fail(STENCIL_E_DEVICE, "no device address for the residual scratch array");
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return STENCIL_OK;
+}
+
+}  // namespace
+
+extern "C" int stencil_residual_noalloc(const void *u, const void *ref, int dtype, int64_t n,
+                                        void *stream, double *out_dev) {
+  using namespace stencil;
+  set_error("");
+  if (!u || !out_dev) return fail(STENCIL_E_ARG, "u and out_dev must be non-NULL");
+  if (dtype != STENCIL_F32 && dtype != STENCIL_F64)
+    return fail(STENCIL_E_ARG, "dtype must be STENCIL_F32 or STENCIL_F64");
+  if (n < 0) return fail(STENCIL_E_ARG, "n must be >= 0");
+  if (kScratchNeed > kScratchDoubles)
+    return fail(STENCIL_E_UNSUPPORTED, "residual partials (" + std::to_string(kScratchNeed) +
+                                           " doubles) exceed the scratch array (" +
+                                           std::to_string(kScratchDoubles) + ")");
+  double *ptr = nullptr;
+  int rc = scratch_on_current_device(&ptr);
+  if (rc != STENCIL_OK) return rc;
+  // n = 0 still runs the kernels: every block writes its partials (zeros),
+  // so out_dev receives 0, 0, 0 without a memset
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_residual(u, ref, dtype, n, ptr, kResidualBlocks, out_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "stencil_residual_noalloc");
+  return STENCIL_OK;
+}
