@@ -3,27 +3,37 @@
 // operands and FP32 accumulation.
 //
 // Folding m steps (Section 3.3) turns a 3x3 box into a dense (2R+1)^2 box,
-// R = m*r, dense enough that one output tile is a sum of matrix products:
-//   out[y0+i][x0+n] = sum_dy sum_k A_dy[i][k] * B_dy[k][n],
-//   A_dy[i][k] = u[y0+i+dy][x0-R+k]           (16 x 32, rows of the input),
-//   B_dy[k][n] = W[dy][k-n-R] if |k-n-R| <= R  (32 x 16, banded Toeplitz),
-// with K = 32 >= 16 + 2R for R <= 8.  Each operand is split into
-// bf16 hi = bf16(x) and lo = bf16(x - hi); three products (hi*hi, hi*lo,
-// lo*hi) recover about 16 significant bits, so the result stays within 1e-3
-// of the FP64 sweep over hundreds of folded steps, unlike a single BF16
-// product.  Unlike the vector kernels this form does not keep the canonical
-// summation order: the matrix unit adds in its own order.
+// R = m*r, dense enough that one output row is a sum of matrix products.
+// For one input row j and one vertical offset dy, the contribution to the
+// output row y = j - dy, for 16 blocks of 16 consecutive columns, is
+//   D[n][i] = sum_k T_dy[n][k] * U_j[k][i],
+//   T_dy[n][k] = W[dy][k - n - R] if |k-n-R| <= R  (16 x 32, banded Toeplitz),
+//   U_j[k][i]  = u[j][16 i - R + k]              (32 x 16: block i's window),
+// with D[n][i] the output at column 16 i + n of the strip and K = 32 >=
+// 16 + 2R for R <= 8.  So each input row is converted to matrix operands
+// once and feeds the 2R+1 output rows it touches (the rows pending in a
+// register queue, as in the vector sweeps): three products per (row, dy),
+// hi*hi, lo*hi and hi*lo of bf16 hi = bf16(x) and lo = bf16(x - hi), all into
+// one FP32 accumulator per pending output row.  The split recovers about 16
+// significant bits, so the result stays within 1e-3 of the FP64 sweep over
+// hundreds of folded steps, unlike a single BF16 product.  The matrix unit
+// adds in its own order, so this form does not keep the canonical summation
+// order.
 //
-// Work layout: a workgroup of 4 wavefronts owns a 128-column strip of a
-// segment of rows; wavefront w computes two 16-column blocks.  Input rows are
-// staged 16 at a time into an LDS ring (64 rows, split into hi and lo planes)
-// one chunk ahead of the products; the B_dy fragments (hi and lo) stay in
-// registers for the whole kernel, loaded from a table the host builds once
-// per operator.
+// Work layout: one wavefront per strip of 256 output columns and a segment
+// of rows, streaming down the rows.  Lane l (i = l % 16, g = l / 16) holds
+// U_j[8g .. 8g+7][i], 8 consecutive input values it loads straight from
+// memory, and the accumulator values D[4g .. 4g+3][i], 4 consecutive output
+// columns it stores with one 16-byte store.  Every input row has a register
+// buffer of its own among 2R+1: the loads of row t+2R+1 are issued while row
+// t is multiplied.  The T_dy fragments (hi and lo) stay in registers for the
+// whole kernel, loaded from a table the host builds once per operator.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <utility>
 
 #include "internal.h"
 
@@ -32,246 +42,244 @@ namespace stencil {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kWaves = 4;
-constexpr int kThreads = 64 * kWaves;
-constexpr int kBlocks = 2;                     // 16-column blocks per wavefront
-constexpr int kStrip = 16 * kWaves * kBlocks;  // output columns per workgroup
-constexpr int kRing = 64;            // staged rows: 4 chunks of 16 (3 in use)
-
-__device__ __forceinline__ unsigned short bf16_bits_rne(float x) {
-  unsigned int u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
+constexpr int kStrip = 256;  // output columns per wavefront (16 blocks of 16)
 
 __device__ __forceinline__ int wrapfull(int i, int n) {
   const int r = i % n;
   return r < 0 ? r + n : r;
 }
 
-// VEC: rows hold a multiple of 4 floats and the input is 16-byte aligned, so
-// staging reads aligned float4 groups (a group never straddles the periodic
-// seam); otherwise one float at a time.
-template <int R, bool VEC>
-__global__ void __launch_bounds__(kThreads)
-k_mfma2d(const float *__restrict__ in, float *__restrict__ out, int ny, int nx, int rows_per_wg,
-         int tiles_x, const uint4 *__restrict__ btab) {
+// Blocks are dealt round-robin to the 8 XCDs (block b to XCD b mod 8):
+// renumber them so that each XCD runs one contiguous range of strips and
+// neighbouring strips share their halo columns in one L2.
+__device__ __forceinline__ int xcd_contiguous(int b, int nb) {
+  const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+  return x * q + min(x, r) + i;
+}
+
+// Calls f(std::integral_constant<int, K>) for K = 0 .. N-1 in order.
+template <typename F, int... Ks>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Ks...>) {
+  (f(std::integral_constant<int, Ks>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// V: floats per load (4: the window starts are multiples of 4, rows hold a
+// multiple of 4 floats and the input is 16-byte aligned, so a vector never
+// straddles the periodic seam; 2 likewise; 1: any shape).  FULL: every
+// strip of the launch holds 256 columns of the grid (x0 + 256 <= nx, nx a
+// multiple of 4, output 16-byte aligned); otherwise the strips start at
+// x_first and are stored column by column.
+template <int R, int V, bool FULL>
+__global__ void __launch_bounds__(64)
+k_mfma2d(const float *__restrict__ in, float *__restrict__ out, int ny, int nx, int rows,
+         int tiles_x, int x_first, const uint4 *__restrict__ btab) {
   static_assert(R >= 1 && R <= 8, "K = 32 covers 16 + 2R columns for R <= 8");
+  static_assert(V == 1 || V == 2 || V == 4, "vector width");
   constexpr int S = 2 * R + 1;
-  constexpr int SW = kStrip + 2 * R;  // staged columns: x = x0 - R + c
-  // an A fragment spans 32 columns from its block's first column, so ring
-  // rows hold kStrip + 16 columns; those past the staged width are zero
-  // (finite, and multiplied by zero weights)
-  constexpr int SWP = kStrip + 16;
-  static_assert(SW <= SWP, "staged width");
-  // staging work per thread per chunk of 16 rows
-  constexpr int NG = SWP / 4;                              // float4 groups per row
-  constexpr int PERV = (16 * NG + kThreads - 1) / kThreads;
-  constexpr int PERS = (16 * SW + kThreads - 1) / kThreads;
-  constexpr int PER = VEC ? PERV : PERS;
-  __shared__ __attribute__((aligned(16))) unsigned short s_hi[kRing][SWP];
-  __shared__ __attribute__((aligned(16))) unsigned short s_lo[kRing][SWP];
-  __shared__ __attribute__((aligned(16))) float s_out[16][kStrip + 4];
-
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  const int li = lane & 15, lg = lane >> 4;
-  const int tile = blockIdx.x;
+  constexpr int NP = 8 / V;  // loads per row and lane
+  const int lane = threadIdx.x;
+  const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
   const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int x0 = tx * kStrip;
-  const int ybase = ty * rows_per_wg;
-  const int yend = min(ybase + rows_per_wg, ny);
-  const int nchunks = (yend - ybase + 15) / 16;
+  const int x0 = x_first + tx * kStrip, y0 = ty * rows;
+  const int nt = min(rows, ny - y0) + 2 * R;  // input rows streamed
 
-  // B_dy fragments (lane (n = li, g = lg) holds k = 8g + j), built once on
-  // the host: btab[(2d) * 64 + lane] = hi, btab[(2d + 1) * 64 + lane] = lo
-  bf16x8 bhi[S], blo[S];
+  // T_dy fragments: lane (n = lane % 16, g = lane / 16) holds k = 8g .. 8g+7;
+  // btab[(2d) * 64 + lane] = hi, btab[(2d + 1) * 64 + lane] = lo, d = dy + R
+  bf16x8 th[S], tl[S];
 #pragma unroll
   for (int d = 0; d < S; ++d) {
-    bhi[d] = __builtin_bit_cast(bf16x8, btab[(2 * d) * 64 + lane]);
-    blo[d] = __builtin_bit_cast(bf16x8, btab[(2 * d + 1) * 64 + lane]);
+    th[d] = __builtin_bit_cast(bf16x8, btab[(2 * d) * 64 + lane]);
+    tl[d] = __builtin_bit_cast(bf16x8, btab[(2 * d + 1) * 64 + lane]);
   }
 
-  // staging step s covers input rows ybase - R + 16s + [0, 16), ring slots
-  // 16*(s % 4) + [0, 16).  A thread stages the same (row, column group)
-  // pairs at every step, so their wrapped columns are computed once; rows
-  // and columns use a full modulo because the staged window may exceed a
-  // small grid several times over.
-  f32x4 pv[PER];
-  int prow[PER], pgx[PER];
+  const int i = lane & 15, g = lane >> 4;
+  const int c0 = x0 + 16 * i - R + 8 * g;  // first input column of the lane's window
+  int col[NP];
 #pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int e = tid + p * kThreads;
-    prow[p] = -1;
-    pgx[p] = 0;
-    if (VEC ? e < 16 * NG : e < 16 * SW) {
-      const int per_row = VEC ? NG : SW;
-      const int r = e / per_row, q = e - r * per_row;
-      prow[p] = r;
-      // VEC: group q covers x = x0 - 8 + 4q .. +3 (aligned, never split by
-      // the seam since nx % 4 == 0); else column q is x = x0 - R + q
-      pgx[p] = wrapfull(VEC ? x0 - 8 + 4 * q : x0 - R + q, nx);
-    }
-  }
-  auto fetch = [&](int s) {
+  for (int p = 0; p < NP; ++p) col[p] = wrapfull(c0 + V * p, nx);
+
+  float buf[S][8];
+  auto load = [&](float(&b)[8], int gy) {
+    const float *src = in + (size_t)gy * nx;
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      if (prow[p] >= 0) {
-        const int gy = wrapfull(ybase - R + 16 * s + prow[p], ny);
-        const float *src = in + (size_t)gy * nx + pgx[p];
-        if constexpr (VEC)
-          pv[p] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(src));
-        else
-          pv[p][0] = __builtin_nontemporal_load(src);
-      }
-    }
-  };
-  // hi = bf16(x), lo = bf16(x - hi), both rounded to nearest even (the
-  // hardware conversion on gfx950)
-  auto split = [](float x, unsigned short &h, unsigned short &l) {
-    const __bf16 hb = (__bf16)x;
-    const __bf16 lb = (__bf16)(x - (float)hb);
-    h = __builtin_bit_cast(unsigned short, hb);
-    l = __builtin_bit_cast(unsigned short, lb);
-  };
-  auto stage = [&](int s) {
-    const int slot0 = 16 * (s & 3);
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      if (prow[p] < 0) continue;
-      const int r = prow[p];
-      if constexpr (VEC) {
-        const int e = tid + p * kThreads;
-        const int q = e - r * NG;
-        const int c0 = 4 * q - 8 + R;  // staged column of the group's first value
-        unsigned short h[4], l[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) split(pv[p][t], h[t], l[t]);
-        if constexpr (R % 4 == 0) {
-          // c0 is a multiple of 4: one 8-byte store per plane
-          if (c0 >= 0 && c0 + 4 <= SW) {
-            uint2 hv = {(unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2] | ((unsigned)h[3] << 16)};
-            uint2 lv = {(unsigned)l[0] | ((unsigned)l[1] << 16), (unsigned)l[2] | ((unsigned)l[3] << 16)};
-            *reinterpret_cast<uint2 *>(&s_hi[slot0 + r][c0]) = hv;
-            *reinterpret_cast<uint2 *>(&s_lo[slot0 + r][c0]) = lv;
-          }
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (c0 + t >= 0 && c0 + t < SW) {
-              s_hi[slot0 + r][c0 + t] = h[t];
-              s_lo[slot0 + r][c0 + t] = l[t];
-            }
-        }
+    for (int p = 0; p < NP; ++p) {
+      if constexpr (V == 4) {
+        const f32x4 v = *reinterpret_cast<const f32x4 *>(src + col[p]);
+        b[4 * p] = v[0]; b[4 * p + 1] = v[1]; b[4 * p + 2] = v[2]; b[4 * p + 3] = v[3];
+      } else if constexpr (V == 2) {
+        const f32x2 v = *reinterpret_cast<const f32x2 *>(src + col[p]);
+        b[2 * p] = v[0]; b[2 * p + 1] = v[1];
       } else {
-        const int e = tid + p * kThreads;
-        const int c = e - r * SW;
-        unsigned short h, l;
-        split(pv[p][0], h, l);
-        s_hi[slot0 + r][c] = h;
-        s_lo[slot0 + r][c] = l;
+        b[p] = src[col[p]];
       }
     }
   };
-
-  for (int e = tid; e < kRing * (SWP - SW); e += kThreads) {
-    const int r = e / (SWP - SW), c = SW + e % (SWP - SW);
-    s_hi[r][c] = 0;
-    s_lo[r][c] = 0;
+  // rows stream from y0 - R; the loads run S rows ahead of the products
+  // (rows past the segment wrap around the grid: always in bounds)
+  int gy = wrapfull(y0 - R, ny);
+#pragma unroll
+  for (int u = 0; u < S; ++u) {
+    load(buf[u], gy);
+    gy = gy + 1 == ny ? 0 : gy + 1;
   }
-  fetch(0);
-  stage(0);
-  fetch(1);
-  stage(1);
-  __syncthreads();
+  f32x4 acc[S];
+#pragma unroll
+  for (int d = 0; d < S; ++d) acc[d] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  const int oc = x0 + 16 * i + 4 * g;  // first output column of the lane
+  float *orow = out + (size_t)y0 * nx + oc;  // output row of step t = 2R
 
-  for (int c = 0; c < nchunks; ++c) {
-    const bool more = c + 2 <= nchunks;  // chunk c+1 will need staging step c+2
-    if (more) fetch(c + 2);
-    // three independent accumulation chains per block (one per product
-    // kind) keep the matrix pipe busy; the two small ones are added first
-    f32x4 acc_lh[kBlocks], acc_hl[kBlocks], acc_hh[kBlocks];
-    // A fragments at step d: lane (i, g) of block b needs staged row
-    // 16c + i + d, columns cb + 8g .. cb + 8g + 7, read from LDS (hi and lo).
-    // (Carrying the lo plane in registers and moving it one row per step
-    // with DPP row_shl/row_ror was measured slower: the moves cost more
-    // VALU issue than the LDS reads they save.)
+  // hi = bf16(x), lo = bf16(x - hi), both rounded to nearest even by the
+  // packed conversion; hi is widened back by a shift or a mask of its pair
+  auto split = [](const float(&x)[8], bf16x8 &h, bf16x8 &l) {
 #pragma unroll
-    for (int b = 0; b < kBlocks; ++b) acc_lh[b] = acc_hl[b] = acc_hh[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 4; ++q) {
+      const bf16x2 p = __builtin_convertvector(f32x2{x[2 * q], x[2 * q + 1]}, bf16x2);
+      const unsigned pu = __builtin_bit_cast(unsigned, p);
+      const float h0 = __builtin_bit_cast(float, pu << 16);
+      const float h1 = __builtin_bit_cast(float, pu & 0xFFFF0000u);
+      const bf16x2 lp = __builtin_convertvector(f32x2{x[2 * q] - h0, x[2 * q + 1] - h1}, bf16x2);
+      h[2 * q] = p[0];
+      h[2 * q + 1] = p[1];
+      l[2 * q] = lp[0];
+      l[2 * q + 1] = lp[1];
+    }
+  };
+
+  // Step t (U = t mod S): input row y0 - R + t from buffer U; the output row
+  // y = y0 + t - R - dy accumulates in slot (t - R - dy) mod S = (U - d) mod
+  // S (d = dy + R), so slot U starts a new row (d = 0) and slot (U + 1) mod
+  // S completes one (d = 2R), stored at the end of the step from t = 2R on.
+  // LOAD: refill buffer U with the row S steps ahead.  (Converting the next
+  // row during this step's products, to overlap the two, needs registers
+  // this form does not have: it measured slower.)
+  auto step = [&](auto uc, int t, auto load_c, auto store_c) {
+    constexpr int U = decltype(uc)::value;
+    constexpr bool LOAD = decltype(load_c)::value, STORE = decltype(store_c)::value;
+    bf16x8 ah, al;
+    split(buf[U], ah, al);
+    if constexpr (LOAD) {
+      load(buf[U], gy);
+      gy = gy + 1 == ny ? 0 : gy + 1;
+    }
+    // the completing slot first, so its products are done by the store
+    constexpr int SC = (U + 1) % S;
 #pragma unroll
-    for (int d = 0; d < S; ++d) {
-      const int slot = (16 * c + li + d) & (kRing - 1);
+    for (int p = 0; p < 3; ++p) {
+      const bf16x8 a = p == 1 ? al : ah;
+      acc[SC] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(p == 2 ? tl[2 * R] : th[2 * R], a,
+                                                        acc[SC], 0, 0, 0);
 #pragma unroll
-      for (int b = 0; b < kBlocks; ++b) {
-        const int col = 16 * (kBlocks * wave + b) + 8 * lg;
-        const bf16x8 h = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&s_hi[slot][col]));
-        const bf16x8 l = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&s_lo[slot][col]));
-        acc_lh[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, bhi[d], acc_lh[b], 0, 0, 0);
-        acc_hl[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, blo[d], acc_hl[b], 0, 0, 0);
-        acc_hh[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, bhi[d], acc_hh[b], 0, 0, 0);
+      for (int d = 0; d < 2 * R; ++d) {
+        const int sl = ((U - d) % S + S) % S;
+        acc[sl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            p == 2 ? tl[d] : th[d], a, (p == 0 && d == 0) ? zero : acc[sl], 0, 0, 0);
       }
     }
-    // D fragment: lane holds column li, rows 4*lg + j.  The workgroup's
-    // 16 x kStrip output tile goes through LDS so that rows leave as whole
-    // 16-byte groups (scattered 4-byte stores of 16-lane rows cost about a
-    // third more HBM write traffic).
+    if constexpr (STORE) {
+      float *dst = orow + (size_t)(t - 2 * R) * nx;
+      if constexpr (FULL) {
+        __builtin_nontemporal_store(acc[SC], reinterpret_cast<f32x4 *>(dst));
+      } else {
 #pragma unroll
-    for (int b = 0; b < kBlocks; ++b) {
-      const int oc = 16 * (kBlocks * wave + b) + li;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        s_out[4 * lg + j][oc] = (acc_lh[b][j] + acc_hl[b][j]) + acc_hh[b][j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < (16 * kStrip / 4) / kThreads; ++p) {
-      const int e = tid + p * kThreads;
-      const int r = e / (kStrip / 4), q = e - r * (kStrip / 4);
-      const int yo = ybase + 16 * c + r, xo = x0 + 4 * q;
-      if (yo < yend) {
-        float *dst = out + (size_t)yo * nx + xo;
-        const f32x4 v = *reinterpret_cast<const f32x4 *>(&s_out[r][4 * q]);
-        if (VEC && xo + 4 <= nx) {
-          __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(dst));
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (xo + t < nx) __builtin_nontemporal_store(v[t], dst + t);
-        }
+        for (int jj = 0; jj < 4; ++jj)
+          if (oc + jj < nx) __builtin_nontemporal_store(acc[SC][jj], dst + jj);
       }
     }
-    if (more) stage(c + 2);
-    __syncthreads();
+  };
+  using yes = std::true_type;
+  using no = std::false_type;
+  // the first 2R steps complete no output row
+  static_for<2 * R>([&](auto k) { step(k, (int)decltype(k)::value, yes{}, no{}); });
+  // whole rounds of S steps: one straight-line body without branches, so
+  // every step's loads are issued where they stand
+  int t0 = 2 * R;
+  for (; t0 + S <= nt; t0 += S)
+    static_for<S>([&](auto k) {
+      constexpr int K = decltype(k)::value;
+      step(std::integral_constant<int, (2 * R + K) % S>{}, t0 + K, yes{}, yes{});
+    });
+  // the last steps (fewer than S) consume buffers already loaded
+  static_for<S - 1>([&](auto k) {
+    constexpr int K = decltype(k)::value;
+    if (t0 + K < nt)
+      step(std::integral_constant<int, (2 * R + K) % S>{}, t0 + K, no{}, yes{});
+  });
+}
+
+// Wavefront slots the device holds at once for a kernel (one wave per block).
+template <typename F>
+int resident_waves(F kernel) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 256 * 4;
   }
+  return std::max(1, cus * per_cu);
+}
+
+template <int R, int V, bool FULL>
+hipError_t launch_rvf(const SweepLaunch &L, int tiles_x, int x_first) {
+  constexpr int S = 2 * R + 1;
+  const int ny = (int)L.g.ny;
+  static const int env_rows = [] {
+    const char *e = std::getenv("STENCIL_MFMA_ROWS");
+    return e ? std::atoi(e) : 0;
+  }();
+  int rows = env_rows;
+  if (rows <= 0) {
+    // one strip per resident wavefront slot, each as tall as that allows
+    static const int slots = resident_waves(k_mfma2d<R, V, true>);
+    const int tiles_y = std::max(1, slots / tiles_x);
+    rows = (ny + tiles_y - 1) / tiles_y;
+  }
+  rows = std::min(std::max(rows, 2 * S), ny);
+  const int tiles_y = (ny + rows - 1) / rows;
+  const int64_t blocks = (int64_t)tiles_x * tiles_y;
+  if (blocks > (1LL << 31) - 1) return hipErrorNotSupported;
+  hipLaunchKernelGGL((k_mfma2d<R, V, FULL>), dim3((unsigned)blocks), dim3(64), 0, L.stream,
+                     (const float *)L.in, (float *)L.out, ny, (int)L.g.nx, rows, tiles_x,
+                     x_first, (const uint4 *)L.op->mfma_b);
+  return hipGetLastError();
+}
+
+// Whole 256-column strips in one launch, the remaining columns (a grid
+// narrower than a strip, or every column when output rows are not whole
+// 16-byte vectors) in a second launch that stores column by column.
+template <int R, int V>
+hipError_t launch_rv(const SweepLaunch &L) {
+  const int nx = (int)L.g.nx;
+  const bool vec_out = nx % 4 == 0 && (uintptr_t)L.out % 16 == 0;
+  const int full = vec_out ? nx / kStrip : 0;
+  if (full > 0) {
+    hipError_t e = launch_rvf<R, V, true>(L, full, 0);
+    if (e != hipSuccess) return e;
+  }
+  const int rest = nx - full * kStrip;
+  if (rest > 0) return launch_rvf<R, V, false>(L, (rest + kStrip - 1) / kStrip, full * kStrip);
+  return hipSuccess;
 }
 
 template <int R>
 hipError_t launch_r(const SweepLaunch &L) {
-  const int ny = (int)L.g.ny, nx = (int)L.g.nx;
-  const int tiles_x = (nx + kStrip - 1) / kStrip;
-  int rows = 0;
-  if (const char *e = std::getenv("STENCIL_MFMA_ROWS")) rows = std::atoi(e);
-  if (rows <= 0) {
-    const int target_y = std::max(1, (4096 + tiles_x - 1) / tiles_x);
-    rows = (ny + target_y - 1) / target_y;
-  }
-  rows = std::max(32, (rows + 15) / 16 * 16);
-  const int tiles_y = (ny + rows - 1) / rows;
-  const int64_t blocks = (int64_t)tiles_x * tiles_y;
-  if (blocks > (1LL << 31) - 1 || !L.op->mfma_b) return hipErrorNotSupported;
-  const bool vec = (nx % 4 == 0) && ((uintptr_t)L.in % 16 == 0) && ((uintptr_t)L.out % 16 == 0);
-  const uint4 *bt = (const uint4 *)L.op->mfma_b;
-  const dim3 grid((unsigned)blocks), blk(kThreads);
-  if (vec)
-    hipLaunchKernelGGL((k_mfma2d<R, true>), grid, blk, 0, L.stream, (const float *)L.in,
-                       (float *)L.out, ny, nx, rows, tiles_x, bt);
-  else
-    hipLaunchKernelGGL((k_mfma2d<R, false>), grid, blk, 0, L.stream, (const float *)L.in,
-                       (float *)L.out, ny, nx, rows, tiles_x, bt);
-  return hipGetLastError();
+  if (!L.op->mfma_b) return hipErrorNotSupported;
+  const int64_t nx = L.g.nx;
+  const uintptr_t a = (uintptr_t)L.in;
+  if constexpr (R % 4 == 0)
+    if (nx % 4 == 0 && a % 16 == 0) return launch_rv<R, 4>(L);
+  if constexpr (R % 2 == 0)
+    if (nx % 2 == 0 && a % 8 == 0) return launch_rv<R, 2>(L);
+  return launch_rv<R, 1>(L);
 }
 
 uint16_t bf16_host(float x) {

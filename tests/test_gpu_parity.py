@@ -209,6 +209,13 @@ MFMA_CASES = [
     ("star2d_m4", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (96, 260), 12, 4),
     ("box2d_plain", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (64, 64), 5, 1),
     ("box2d_m2_aligned", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (512, 1024), 8, 2),
+    # whole 256-column strips only, with 16-byte loads and stores (the
+    # launch the 16384^2 workload makes), several row segments
+    ("box2d_m8_full", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (300, 768), 16, 8),
+    # 8-byte loads, whole strips plus a 4-column remainder strip
+    ("box2d_m6_rest", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (200, 516), 12, 6),
+    # a grid narrower than one strip and shorter than the folded halo twice
+    ("box2d_m3_narrow", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (9, 100), 9, 3),
 ]
 
 
