@@ -3,17 +3,26 @@
 MI355X, reported as GStencil/s (grid points x original time steps per second)
 and as a fraction of the roofline that bounds the dominant kernel.
 
-Default workload: the 2D 5-point star (centre 0.6, neighbours 0.1, FP32
-weights), 8192 x 8192 FP32 periodic grid, T = 1000 original steps, uniform
-[0, 1) initial values (SplitMix64, seed 2103).  One step = one stencil_run of
-all T steps (plan and folded weights prepared beforehand, grid resident in
-HBM).  Forms: the plain sweep and the folds m = 2 and m = 4 (13- and 41-point
-folded operators), each as one launch per application ("vector_unfused"),
-with several applications fused per launch ("vector", temporal blocking),
-and with mirrored partial sums shared ("symmetric"); the fastest form of a
-stated fold depth is the headline, all of them are listed under "forms".
+Default run: the five measured workloads, each with all of its forms (plain,
+folded, matrix-core, batched), every result checked against the FP64 oracle:
+  star2d   2D 5-point star (centre 0.6, neighbours 0.1), 8192^2 FP32, T=1000,
+           plain and folds m=2, m=4 -- the headline of the JSON line;
+  heat1d   1D 3-point heat (0.25, 0.5, 0.25), 1,000,000 points FP64, T=100;
+  star3d   3D 7-point star (0.4; 0.1), 512^3 FP32, T=200, plain and m=2;
+  box3d    3D 27-point random positive box, 512^3 FP32, T=200, plain and m=2;
+  box2d    2D 9-point random positive box, 16384^2 FP32, T=400, plain, m=4
+           (9x9) and m=8 (17x17), vector and BF16x3 matrix-core forms;
+  batched  4096 periodic 2D grids, sides log-uniform in [64, 1024], 5-point
+           star or 9-point box, FP32, T=50, one hipGraph of persistent and
+           fused launches against one stencil_run per grid.
+Inputs are synthetic (SplitMix64, seed 2103), uniform [0, 1).  One step of a
+form = one stencil_run of all T original steps with the plan and folded
+weights prepared beforehand and the grid resident in HBM.
 
-Other workloads (--workload): heat1d, star3d, box3d, box2d, batched.
+The line's top-level fields describe star2d's fastest form; "configs" holds
+the same fields for every workload.  --workload X runs one workload alone
+(profiling runs), and also the Table 1 extras (box1d5p, apop1d, life2d,
+unitbox2d, star2d_dirichlet).
 
 Prints ONE JSON line on stdout.
 """
@@ -25,6 +34,7 @@ import hashlib
 import json
 import math
 import os
+import platform
 import re
 import sys
 import time
@@ -32,22 +42,23 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-FP32_VECTOR_TFLOPS = 157.3      # MI355X FP32 vector, published (packed FP32 FMAs)
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0           # HBM3E
+FP32_VECTOR_TFLOPS = 157.3      # FP32 vector (counts packed FP32 FMAs)
+FP64_VECTOR_TFLOPS = 78.6       # FP64 vector
+BF16_MFMA_TFLOPS = 2500.0       # dense BF16 matrix
 # FP32 FMA issue rate without packed FP32 (the kernels are built with packed
 # FP32 disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
 FP32_FMA_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-FP32_FMA_BASIS = ("FP32 FMA issue rate without packed FP32: 256 CUs x 64 lanes x 2 flop x "
-                  "2.4 GHz = 78.6 TFLOP/s (the published 157.3 counts packed FP32 FMAs, "
-                  "which these kernels do not use)")
-FP64_VECTOR_TFLOPS = 78.6       # MI355X FP64 vector, published
-BF16_MFMA_TFLOPS = 2500.0       # MI355X dense BF16 matrix, published
 METRIC = "GStencil/s and % HBM roofline, plain vs folded/MFMA/batched at stated error"
 VALU32_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit VALU lane-operations per second (x1e12)
 # fused Game of Life: VALU instructions per wavefront row (64 words of 4
 # cells) and generation, 15.6-16.1 in the gfx950 assembly of the loop (16
 # and 4 generations per launch)
 LIFE_VALU_PER_ROW_GEN = 16.0
+DEFAULT_SET = ("star2d", "heat1d", "star3d", "box3d", "box2d", "batched")
+GATE = {"vector": 0.0, "vector_graph": 0.0, "vector_unfused": 0.0, "symmetric": 1e-5,
+        "separable": 1e-5, "mfma_bf16x3": 1e-3}
 
 
 def log(*a):
@@ -59,11 +70,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="star2d",
-                    choices=["star2d", "heat1d", "star3d", "box3d", "box2d", "unitbox2d",
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "star2d", "heat1d", "star3d", "box3d", "box2d", "unitbox2d",
                              "star2d_dirichlet", "box1d5p", "apop1d", "life2d", "batched"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-oracle", action="store_true",
+                    help="skip the FP64 oracle reference (profiling runs)")
+    ap.add_argument("--cpu-seconds", type=float, default=0.0,
+                    help="CPU oracle sample per workload (default 10 s alone, 6 s in the "
+                         "default run)")
     ap.add_argument("--only-m", type=int, default=0,
                     help="time only this fold depth (profiling runs)")
     ap.add_argument("--only-mode", default="",
@@ -73,11 +88,22 @@ def parse():
     ap.add_argument("--no-per-grid", action="store_true",
                     help="batched: skip the per-grid-launch baseline (profiling runs)")
     ap.add_argument("--tune-cache", default="",
-                    help="batched: fold-depth tuning cache file to use (and fill); "
-                         "default a fresh temporary file")
+                    help="batched: tuning cache file to use (and fill); default a fresh "
+                         "temporary file")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy (PMC byte-counter calibration)")
     return ap.parse_args()
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 # Source files holding each kernel family's device code: a committed PMC
@@ -123,7 +149,36 @@ def traffic_from_profiles(kernel_key: str, workload: str, field: str = "hbm-byte
     return float(b.group(1)) if b else None
 
 
+def roofline(algo_bytes: float, flops: float, dur_s: float, peak_tflops: float, basis: str,
+             unit_kind: str = "alu", force_hbm: bool = False) -> dict:
+    """The roofline of one launch against MI355X's published peaks: the
+    kernel's algorithmic intensity (flops per algorithmic HBM byte) against
+    the ridge peak / 8 TB/s decides the bound; frac = achieved / peak of that
+    bound, which is also achieved / min(peak, intensity x 8 TB/s)."""
+    intensity = flops / algo_bytes if algo_bytes else float("inf")
+    ridge = peak_tflops * 1e12 / (HBM_PEAK_GBS * 1e9)
+    gbs = algo_bytes / dur_s / 1e9
+    tfl = flops / dur_s / 1e12
+    if intensity < ridge or force_hbm:
+        r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        r = {"bound": unit_kind, "achieved": round(tfl, 2), "peak": peak_tflops,
+             "unit": "TFLOP/s"}
+    r["frac"] = round(r["achieved"] / r["peak"], 4)
+    r["intensity_flop_per_byte"] = round(intensity, 3)
+    r["compute_peak"] = {"tflops": peak_tflops, "basis": basis}
+    r["attainable_tflops"] = round(min(peak_tflops, intensity * HBM_PEAK_GBS / 1e3), 2)
+    r["achieved_gbs"] = round(gbs, 1)
+    r["achieved_tflops"] = round(tfl, 2)
+    r["launch_ms"] = round(dur_s * 1e3, 5)
+    r["algorithmic_bytes_per_launch"] = int(algo_bytes)
+    r["algorithmic_flops_per_launch"] = float(flops)
+    return r
+
+
 def time_runs(fn, steps, warmup):
+    """Seconds of `steps` calls between two HIP events on the current stream
+    (the stream the library launches on), after `warmup` untimed calls."""
     import torch
     for _ in range(warmup):
         fn()
@@ -140,10 +195,11 @@ def time_runs(fn, steps, warmup):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
-def cpu_baseline(w, shape_full, dtype, T_full, budget_s, boundary="periodic"):
+def cpu_baseline(w, shape_full, T_full, budget_s, boundary="periodic"):
     """The oracle as it stands, timed on a bounded sample of the workload: a
-    smaller grid of the same dimension and distribution, for a number of
-    original steps chosen to fill about budget_s seconds."""
+    smaller grid of the same dimension and distribution (the full grid when
+    it fits the budget), for a number of original steps chosen to fill about
+    budget_s seconds."""
     import numpy as np
     import oracle
     import synth
@@ -175,35 +231,49 @@ def cpu_baseline(w, shape_full, dtype, T_full, budget_s, boundary="periodic"):
         "value": round(n * T / dt / 1e9, 4),
         "unit": "GStencil/s",
         "cores": oracle.num_threads(),
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": "FP64 naive sweep, grid %s, %d of the %d original steps, %.1f s" % (
             "x".join(map(str, shape)), T, T_full, dt),
     }
 
 
-def fp64_reference(sf, w, kind, u0, T, boundary=0):
-    """The same T steps in FP64 by the library's plain FP64 sweep, which the
-    parity tests pin bit-for-bit to the FP64 oracle."""
+def oracle_reference(w, u0, T, boundary="periodic"):
+    """u_T in FP64 from the oracle: the naive loop where it finishes in a few
+    seconds (bit-exact definition), else its spectral form (the same operator
+    diagonalised by the DFT, or by the sine transform for zero ghosts;
+    rounding of order eps log N)."""
     import numpy as np
-    import torch
-    plan = sf.Plan(w, kind, boundary)
-    d = torch.from_numpy(np.asarray(u0, dtype=np.float64)).cuda()
-    plan.run(d, T)
-    torch.cuda.synchronize()
-    plan.close()
-    return d
+    import oracle
+    u64 = np.asarray(u0, dtype=np.float64)
+    taps = int(np.count_nonzero(w))
+    if u64.size * T * taps <= 4e9:
+        return oracle.sweep(w, u64, T, boundary), "oracle.sweep (naive FP64 loop, canonical order)"
+    return (oracle.sweep_spectral(w, u64, T, boundary),
+            "oracle.sweep_spectral (FP64, eigen-decomposition of the operator)")
 
 
 def error_vs(ref64, got):
+    """e_rel = max|u - ref| / max|ref| and e_detr = max|u - ref| / max|ref -
+    mean(ref)| (the oracle's error metrics, evaluated on the GPU for full
+    grids), and the count of elements equal to the reference."""
     import torch
     d = (got.double() - ref64).abs().max().item()
     nref = ref64.abs().max().item()
     mean = ref64.mean().item()
     ndet = (ref64 - mean).abs().max().item()
-    return d / nref, d / ndet if ndet > 0 else d
+    same = int((got.double() == ref64).sum().item())
+    return d / nref if nref > 0 else d, d / ndet if ndet > 0 else d, same
 
 
-def bench_grid(args, wl_name):
+def budget_s(args, default_run):
+    return args.cpu_seconds if args.cpu_seconds > 0 else (6.0 if default_run else 10.0)
+
+
+def bench_grid(args, wl_name, default_run=False):
+    """One single-grid workload: every form timed, each one's T-step result
+    checked against the FP64 oracle, the fastest form within its error gate
+    reported with the roofline of its dominant kernel."""
     import numpy as np
     import torch
     import synth
@@ -216,6 +286,7 @@ def bench_grid(args, wl_name):
     f32 = wl.dtype == "f32"
     esz = 4 if f32 else 8
     n = int(np.prod(shape))
+    r = (w.shape[0] - 1) // 2
     log("[bench] workload %s: %s" % (wl_name, wl.note))
     u0 = synth.grid_f32(shape) if f32 else synth.grid_f64(shape)
     dev = torch.device("cuda:0")
@@ -223,12 +294,20 @@ def bench_grid(args, wl_name):
     scratch = torch.empty_like(data)
     s0, _, _ = sf.stencil_residual(data)
 
+    ref64, ref_kind = None, None
+    if not args.no_oracle:
+        log("[bench] FP64 oracle reference of T=%d steps" % T)
+        t0 = time.perf_counter()
+        ref_host, ref_kind = oracle_reference(w, u0, T, "zero" if zero_bc else "periodic")
+        ref64 = torch.from_numpy(ref_host).to(dev)
+        del ref_host
+        log("[bench]   %s, %.1f s" % (ref_kind, time.perf_counter() - t0))
+
     forms = {}
-    ref64 = None
-    headline = None
+    best = None
     symmetric = wl.dim == 2 and np.array_equal(w, w[::-1, :]) and np.array_equal(w, w[:, ::-1])
     # extra fold depths beyond the workload's stated ones are reported under
-    # "forms" but never chosen as the headline
+    # "forms" but never chosen as the workload's result
     extra = {"star2d": (8,)}.get(wl_name, ())
     for m in tuple(wl.folds) + extra:
         if args.only_m and m != args.only_m:
@@ -282,22 +361,22 @@ def bench_grid(args, wl_name):
             # mass after the timed runs: data has advanced (warmup+steps)*T steps
             total_T = (args.warmup + args.steps) * T
             s1, _, _ = sf.stencil_residual(data)
-            w_eff = w.astype(np.float32).astype(np.float64) if f32 else w
-            expect = math.fsum(float(v) for v in w_eff.ravel()) ** total_T * s0
+            expect = math.fsum(float(v) for v in w.ravel()) ** total_T * s0
             # (zero boundaries lose mass through the faces: not an invariant)
             mass_rel = None if zero_bc else abs(s1 - expect) / abs(expect)
-            # error of one T-step run against the FP64 sweep
+            # one T-step run from u0 against the oracle
             data.copy_(torch.from_numpy(u0).to(dev))
             plan.run(data, T, scratch)
-            if ref64 is None:
-                ref64 = fp64_reference(sf, w, wl.shape_kind, u0, T, bc)
-            err, err_detr = error_vs(ref64, data)
+            err = err_detr = None
+            same = None
+            if ref64 is not None:
+                err, err_detr, same = error_vs(ref64, data)
             gst = n * T * args.steps / el / 1e9
             launches = sched["folded_launches"] + sched["plain_launches"]
             # the dominant kernel: the folded pass when there is one
             dom = "folded" if sched["folded_launches"] else "plain"
             per_launch = sched[dom + "_apps"] / sched[dom + "_launches"]
-            launch_ms = el / args.steps / launches * 1e3
+            launch_s = el / args.steps / launches
             algo_bytes = 2 * esz * n
             taps = int(np.count_nonzero(plan.fold(m) if m > 1 else w))
             # flops the form executes per point: one FMA per tap, or for the
@@ -305,63 +384,66 @@ def bench_grid(args, wl_name):
             # pass per rank-one term)
             fmas = taps
             if mode_name == "separable":
-                fmas = 2 * plan.separable()[0] * (2 * m * ((w.shape[0] - 1) // 2) + 1)
+                fmas = 2 * plan.separable()[0] * (2 * m * r + 1)
             flops = 2 * fmas * n * per_launch
             key = "%s_m%d_%s" % (wl_name, m, mode_name)
+            gate = (1e-3 if mode_name == "mfma_bf16x3" else 1e-5) if f32 else 1e-12
             forms[key] = {
                 "m": m, "mode": mode_name, "gstencil_s": round(gst, 2),
                 "ms_per_run": round(el / args.steps * 1e3, 4),
                 "launches_per_run": launches,
                 "applications_per_launch": round(per_launch, 3),
-                "ms_per_launch": round(launch_ms, 5), "taps": taps,
+                "ms_per_launch": round(launch_s * 1e3, 5), "taps": taps,
                 "fmas_per_point": fmas,
-                "hbm_gbs_algorithmic": round(algo_bytes / (launch_ms / 1e3) / 1e9, 1),
-                "hbm_frac": round(algo_bytes / (launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                "alu_tflops": round(flops / (launch_ms / 1e3) / 1e12, 2),
-                "e_rel_vs_fp64": err, "e_detrended_vs_fp64": err_detr,
+                "hbm_gbs_algorithmic": round(algo_bytes / launch_s / 1e9, 1),
+                "hbm_frac": round(algo_bytes / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                "tflops": round(flops / launch_s / 1e12, 2),
+                "e_rel_vs_oracle": err, "e_detrended_vs_oracle": err_detr,
+                "equal_to_oracle": same, "gate": gate,
+                "within_gate": None if err is None else bool(err <= gate),
                 "mass_rel_drift": mass_rel, "mass_T": total_T,
                 "wall_s": round(wall, 3),
             }
             log("[bench]   %.1f GStencil/s, %d launches of %.2f applications, %.4f ms/launch, "
-                "e_rel %.2e (detrended %.2e), mass drift %s" % (
-                    gst, launches, per_launch, launch_ms, err, err_detr,
+                "e_rel %s (detrended %s), mass drift %s" % (
+                    gst, launches, per_launch, launch_s * 1e3,
+                    "n/a" if err is None else "%.2e" % err,
+                    "n/a" if err_detr is None else "%.2e" % err_detr,
                     "n/a" if mass_rel is None else "%.2e" % mass_rel))
             forms[key]["stated_fold"] = m not in extra
+            Rf = m * r
             if mode_name == "mfma_bf16x3":
-                # matrix-core work issued: per dy three 16x16x32 products
-                # (hi*hi, hi*lo, lo*hi) per 16x16 output block, 64 flop per
-                # point each, over 2R+1 values of dy
-                Rf = m * ((w.shape[0] - 1) // 2)
+                # matrix-core work issued: per input row and dy three 16x16x32
+                # products (hi*hi, lo*hi, hi*lo) per 16-column block, 64 flop
+                # per output point each, over 2R+1 values of dy
                 issued = 3 * (2 * Rf + 1) * 64.0 * n * per_launch
                 forms[key]["mfma_issued_flop_per_point"] = int(3 * (2 * Rf + 1) * 64)
-                forms[key]["mfma_issued_tflops"] = round(issued / (launch_ms / 1e3) / 1e12, 1)
-                forms[key]["mfma_util_of_bf16_peak"] = round(
-                    issued / (launch_ms / 1e3) / 1e12 / BF16_MFMA_TFLOPS, 4)
-            if m not in extra and (headline is None or gst > headline[1]):
-                headline = (key, gst, el, launch_ms, algo_bytes, flops, m, mode_name, taps,
-                            per_launch)
+                forms[key]["mfma_issued_tflops"] = round(issued / launch_s / 1e12, 1)
+                forms[key]["mfma_issued_frac_of_bf16_peak"] = round(
+                    issued / launch_s / 1e12 / BF16_MFMA_TFLOPS, 4)
+            ok = err is None or err <= gate
+            if m not in extra and ok and (best is None or gst > best[1]):
+                best = (key, gst, el, launch_s, algo_bytes, flops, m, mode_name, taps,
+                        per_launch)
             plan.close()
-    key, gst, el, launch_ms, algo_bytes, flops, m, mode_name, taps, per_launch = headline
-    intensity = flops / algo_bytes
+    key, gst, el, launch_s, algo_bytes, flops, m, mode_name, taps, per_launch = best
     if mode_name.startswith("mfma"):
-        peak_t, basis = BF16_MFMA_TFLOPS, "dense BF16 matrix, published"
+        peak_t, basis, kind = BF16_MFMA_TFLOPS, "dense BF16 matrix, published", "mfma"
     elif f32:
-        peak_t, basis = FP32_FMA_TFLOPS, FP32_FMA_BASIS
+        peak_t, basis, kind = FP32_VECTOR_TFLOPS, "FP32 vector, published", "alu"
     else:
-        peak_t, basis = FP64_VECTOR_TFLOPS, "FP64 vector, published"
-    ridge = peak_t * 1e12 / (HBM_PEAK_GBS * 1e9)
-    dur = launch_ms / 1e3
-    # the matrix-core form is priced against HBM (its MFMA rate is far from
-    # bound); the symmetric form executes fewer operations than its taps
-    if intensity < ridge or mode_name in ("mfma_bf16x3", "symmetric"):
-        roof = {"bound": "hbm", "achieved": round(algo_bytes / dur / 1e9, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    else:
-        roof = {"bound": "alu", "achieved": round(flops / dur / 1e12, 2),
-                "peak": peak_t, "unit": "TFLOP/s", "peak_basis": basis}
-        if f32:
-            roof["frac_of_published_fp32_vector"] = round(roof["achieved"] / FP32_VECTOR_TFLOPS, 4)
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+        peak_t, basis, kind = FP64_VECTOR_TFLOPS, "FP64 vector, published", "alu"
+    # the symmetric form executes fewer operations than its dense taps: it is
+    # priced by its bytes only
+    roof = roofline(algo_bytes, flops, launch_s, peak_t, basis, kind,
+                    force_hbm=mode_name == "symmetric")
+    if f32 and not mode_name.startswith("mfma"):
+        # the FP32 FMA issue rate these kernels can reach (packed FP32 off)
+        roof["fp32_fma_issue_frac"] = round(flops / launch_s / 1e12 / FP32_FMA_TFLOPS, 4)
+        roof["fp32_fma_issue_basis"] = ("256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz = "
+                                        "78.6 TFLOP/s (FMAs, packed FP32 not used)")
+    if mode_name.startswith("mfma"):
+        roof["mfma_issued_frac_of_bf16_peak"] = forms[key]["mfma_issued_frac_of_bf16_peak"]
     fused = per_launch > 1 and wl.dim == 2
     tkey = {"vector": ("sweep%dd%s_m%d" % (wl.dim, "tb" if fused else "", m)),
             "vector_graph": ("sweep%dd%s_m%d" % (wl.dim, "tb" if fused else "", m)),
@@ -373,13 +455,20 @@ def bench_grid(args, wl_name):
     roof["kernel"] = "%s R=%d (%s, %d taps, %.2f applications per launch)" % (
         "k_sweep2d_tb" if fused else ("k_mfma2d" if mode_name.startswith("mfma")
                                       else "k_sweep%dd" % wl.dim),
-        m * ((w.shape[0] - 1) // 2), mode_name, taps, per_launch)
-    roof["launch_ms"] = round(launch_ms, 5)
-    roof["algorithmic_bytes_per_launch"] = algo_bytes
-    roof["algorithmic_flops_per_launch"] = flops
+        m * r, mode_name, taps, per_launch)
     roof["flops_basis"] = ("2 x FMAs per point (dense taps; 2 x rank x (2R+1) for the separable "
                            "form) x points x applications per launch")
-    roof["hbm_frac"] = round(algo_bytes / dur / 1e9 / HBM_PEAK_GBS, 4)
+    # speedups of the folded / matrix-core forms over the plain sweep
+    plain_fused = forms.get("%s_m1_vector" % wl_name, {}).get("gstencil_s")
+    plain_unfused = (forms.get("%s_m1_vector_unfused" % wl_name, {}).get("gstencil_s")
+                     or plain_fused)
+    speedups = {}
+    for k, f in forms.items():
+        if f["m"] > 1 or f["mode"] not in ("vector", "vector_unfused"):
+            if plain_unfused:
+                speedups[k] = {"vs_plain_one_step_launches": round(f["gstencil_s"] / plain_unfused, 3)}
+                if plain_fused:
+                    speedups[k]["vs_plain_fused"] = round(f["gstencil_s"] / plain_fused, 3)
     res = {
         "metric": METRIC,
         "value": round(gst, 2),
@@ -396,16 +485,22 @@ def bench_grid(args, wl_name):
         "config": {"workload": wl.note, "grid": list(shape), "T": T, "fold_m": m,
                    "mode": mode_name, "points": n},
         "roofline": roof,
+        "error_vs_oracle": {"e_rel": forms[key]["e_rel_vs_oracle"],
+                            "e_detrended": forms[key]["e_detrended_vs_oracle"],
+                            "equal_elements": forms[key]["equal_to_oracle"],
+                            "gate": forms[key]["gate"], "reference": ref_kind},
         "forms": forms,
+        "speedups": speedups,
     }
+    del ref64
     if not args.no_cpu:
         log("[bench] timing the CPU oracle baseline")
-        res["cpu_baseline"] = cpu_baseline(w, shape, wl.dtype, T, args.cpu_seconds,
+        res["cpu_baseline"] = cpu_baseline(w, shape, T, budget_s(args, default_run),
                                            "zero" if zero_bc else "periodic")
     return res
 
 
-def bench_batched(args):
+def bench_batched(args, default_run=False):
     """4096 independent periodic 2D grids, sides log-uniform in [64, 1024],
     each a 5-point star or 9-point box with random positive weights summing
     to 1, FP32, T = 50.  Forms: one persistent launch per (folded) sweep in a
@@ -415,6 +510,7 @@ def bench_batched(args):
     import numpy as np
     import tempfile
     import torch
+    import oracle
     import synth
     import paper_2103_09235_amd as sf
 
@@ -483,6 +579,20 @@ def bench_batched(args):
         w32 = weights[i].astype(np.float32).astype(np.float64)
         expect = math.fsum(float(v) for v in w32.ravel()) ** T * s0[i]
         drift = max(drift, abs(sf.stencil_residual(datas[i])[0] - expect) / abs(expect))
+    # the same run against the FP64 oracle on every 64th grid
+    err = {"e_rel_max": None, "grids_checked": 0}
+    if not args.no_oracle:
+        log("[bench] FP64 oracle on every 64th grid")
+        worst = worst_d = 0.0
+        checked = 0
+        for i in range(0, count, 64):
+            ref, kind = oracle_reference(weights[i], u0s[i], T)
+            e = oracle.errors(datas[i].cpu().numpy(), ref)
+            worst = max(worst, e["e_rel"])
+            worst_d = max(worst_d, e["e_detr"])
+            checked += 1
+        err = {"e_rel_max": worst, "e_detrended_max": worst_d, "grids_checked": checked,
+               "gate": 1e-5, "reference": kind}
     ms = chosen["tuned"]
     # The time loop is one graph of fused passes (several applications per
     # launch, grids of >= 256 columns), one-step launches and a copy back of
@@ -505,24 +615,18 @@ def bench_batched(args):
         flops_total += 2 * n2 * (apps_f * taps_of[(k, m)] + apps_p * taps_of[(k, 1)])
         bytes_total += 2 * 4 * n2 * ps
     run_s = t_tuned
-    gbs = bytes_total / run_s / 1e9
-    tfl = flops_total / run_s / 1e12
-    if gbs / HBM_PEAK_GBS >= tfl / FP32_FMA_TFLOPS:
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    else:
-        roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_FMA_TFLOPS,
-                "unit": "TFLOP/s", "peak_basis": FP32_FMA_BASIS,
-                "frac_of_published_fp32_vector": round(tfl / FP32_VECTOR_TFLOPS, 4)}
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    # the whole run as one launch unit (its fused, one-step and copy
+    # launches together), priced against the published FP32 peak
+    roof = roofline(bytes_total, flops_total, run_s, FP32_VECTOR_TFLOPS,
+                    "FP32 vector, published", "alu")
+    roof["fp32_fma_issue_frac"] = round(flops_total / run_s / 1e12 / FP32_FMA_TFLOPS, 4)
+    roof["fp32_fma_issue_basis"] = ("256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz = "
+                                    "78.6 TFLOP/s (FMAs, packed FP32 not used)")
     roof["traffic"] = traffic_from_profiles("batched", "batched", "hbm-bytes-per-run")
     roof["traffic_unit"] = "HBM bytes per run (PMC FETCH_SIZE + WRITE_SIZE, calibrated)"
     roof["kernel"] = ("whole time loop: k_batched_tb fused passes + k_batched one-step "
                       "launches + copy back (one hipGraph)")
-    roof["run_ms"] = round(run_s * 1e3, 4)
-    roof["algorithmic_bytes_per_run"] = int(bytes_total)
-    roof["algorithmic_flops_per_run"] = int(flops_total)
-    roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
-    roof["alu_frac"] = round(tfl / FP32_FMA_TFLOPS, 4)
+    roof["launch_unit"] = "one T-step run (all of its launches)"
     roof["passes_per_grid_mean"] = round(sum(passes) / len(passes), 3)
     # the tuned strip heights per (stencil, radius, size class), from the cache
     heights = {}
@@ -551,12 +655,13 @@ def bench_batched(args):
         "speedup_vs_per_grid_launches": round(t_pg / t_tuned, 2) if t_pg else None,
         "speedup_tuned_vs_m1": round(t_m1 / t_tuned, 3) if t_m1 else None,
         "mass_rel_drift_max_64_grids": drift,
+        "error_vs_oracle": err,
     }
     for p in plans:
         p.close()
     if not args.no_cpu:
         log("[bench] timing the CPU oracle baseline")
-        res["cpu_baseline"] = cpu_baseline_batched(weights, u0s, T, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline_batched(weights, u0s, T, budget_s(args, default_run))
     return res
 
 
@@ -580,6 +685,7 @@ def cpu_baseline_batched(weights, grids, T, budget_s):
         "value": round(pts * T / spent / 1e9, 4),
         "unit": "GStencil/s",
         "cores": oracle.num_threads(),
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": "FP64 naive sweep of the batch's first %d grids (%d points, sides %d..%d), "
                   "all %d steps each, %.1f s" % (k, pts, min(g.shape[0] for g in grids[:k]),
@@ -654,12 +760,12 @@ def bench_apop(args):
         t0 = time.perf_counter()
         oracle.floor_sweep(w, payoff[:m], payoff[:m], 2)
         per = (time.perf_counter() - t0) / 2
-        Ts = int(max(1, min(T, args.cpu_seconds / per)))
+        Ts = int(max(1, min(T, budget_s(args, False) / per)))
         t0 = time.perf_counter()
         oracle.floor_sweep(w, payoff[:m], payoff[:m], Ts)
         dt = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": round(m * Ts / dt / 1e9, 4), "unit": "GStencil/s",
-                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "cores": oracle.num_threads(), "cpu_model": cpu_model(), "kind": "oracle",
                                "sample": "FP64 floor sweep on the first %d points (periodic), "
                                          "%d of the %d steps, %.1f s" % (m, Ts, T, dt)}
     return res
@@ -716,15 +822,24 @@ def bench_life(args):
         t0 = time.perf_counter()
         oracle.life(sample, 2)
         per = (time.perf_counter() - t0) / 2
-        Ts = int(max(1, min(T, args.cpu_seconds / per)))
+        Ts = int(max(1, min(T, budget_s(args, False) / per)))
         t0 = time.perf_counter()
         oracle.life(sample, Ts)
         dt = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": round(sample.size * Ts / dt / 1e9, 4),
-                               "unit": "GStencil/s", "cores": 1, "kind": "oracle",
+                               "unit": "GStencil/s", "cores": 1, "cpu_model": cpu_model(), "kind": "oracle",
                                "sample": "numpy Game of Life on a 1000x1000 corner, %d of the "
                                          "%d generations, %.1f s" % (Ts, T, dt)}
     return res
+
+
+
+def config_entry(res: dict) -> dict:
+    """The per-workload record of the default run: the workload's JSON line
+    without the fields that only the top level carries."""
+    drop = ("metric", "n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline",
+            "data")
+    return {k: v for k, v in res.items() if k not in drop}
 
 
 def main():
@@ -749,14 +864,30 @@ def main():
         print(json.dumps({"metric": "copy calibration", "bytes_read_per_launch": 4 * n,
                           "bytes_written_per_launch": 4 * n, "launches": 4}), flush=True)
         return
-    if args.workload == "batched":
-        res = bench_batched(args)
-    elif args.workload == "apop1d":
-        res = bench_apop(args)
-    elif args.workload == "life2d":
-        res = bench_life(args)
-    else:
-        res = bench_grid(args, args.workload)
+
+    def one(name, default_run):
+        if name == "batched":
+            return bench_batched(args, default_run)
+        if name == "apop1d":
+            return bench_apop(args)
+        if name == "life2d":
+            return bench_life(args)
+        return bench_grid(args, name, default_run)
+
+    if args.workload != "all":
+        print(json.dumps(one(args.workload, False)), flush=True)
+        return
+    t_start = time.perf_counter()
+    results = {}
+    for name in DEFAULT_SET:
+        t0 = time.perf_counter()
+        results[name] = one(name, True)
+        torch.cuda.empty_cache()
+        log("[bench] %s done: %.1f GStencil/s (%.0f s)" % (name, results[name]["value"],
+                                                          time.perf_counter() - t0))
+    res = dict(results["star2d"])
+    res["configs"] = {name: config_entry(r) for name, r in results.items()}
+    res["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(res), flush=True)
 
 

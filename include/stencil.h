@@ -184,8 +184,10 @@ int stencil_plan_set_boundary_value(stencil_plan p, double value);
  * hipGraph, captured on a private stream, and replays it on g->stream; the
  * graph is kept per (data, scratch, shape, dtype, T) and dropped when the
  * plan changes (fold depth, mode, fusion, floor).  Results equal the direct
- * launches bit for bit.  Zero-boundary runs always launch directly.
- * 0 = launch directly (default).  Errors: E_ARG.  No device work.
+ * launches bit for bit.  Zero-boundary runs, and runs of at most 4
+ * launches (a replay costs more than that many direct launches), always
+ * launch directly.  0 = launch directly (default).  Errors: E_ARG.  No
+ * device work.
  */
 int stencil_plan_set_graph(stencil_plan p, int on);
 

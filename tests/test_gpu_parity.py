@@ -801,16 +801,17 @@ def test_batched_narrow_strips_bit_exact(tmp_path, T, m, rows):
 
 
 GRAPH_CASES = [
-    # (name, weights, kind, shape, T, m, mode, dtype, caller scratch)
-    ("star2d_fused_odd", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (300, 1024), 37, 1,
+    # (name, weights, kind, shape, T, m, mode, dtype, caller scratch); every
+    # run makes more than 4 launches (shorter runs are never captured)
+    ("star2d_fused_odd", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (300, 1024), 75, 1,
      "vector", np.float32, True),
-    ("star2d_m4_plan_scratch", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (257, 1031), 14,
+    ("star2d_m4_plan_scratch", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (257, 1031), 42,
      4, "vector", np.float32, False),
-    ("box2d_m8_mfma", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (140, 530), 16, 8, "mfma",
+    ("box2d_m8_mfma", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (140, 530), 56, 8, "mfma",
      np.float32, True),
-    ("heat1d_f64", synth.heat1d_weights(), sf.STENCIL_STAR, (100_003,), 37, 1, "vector", np.float64,
+    ("heat1d_f64", synth.heat1d_weights(), sf.STENCIL_STAR, (100_003,), 237, 1, "vector", np.float64,
      True),
-    ("star3d_m2", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (20, 33, 70), 7, 2, "vector",
+    ("star3d_m2", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (20, 33, 70), 13, 2, "vector",
      np.float32, True),
     ("box2d_exact", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (61, 99), 5, 1, "exact",
      np.float32, False),
@@ -842,6 +843,9 @@ def test_run_graph_replays_equal_direct_launches(case):
         ref = (oracle.folded_reference_f32(w, u0, T, m) if dt == np.float32
                else oracle.sweep(w, u0, T))
         assert np.array_equal(direct, ref)
+    sched = plan.schedule(data, T, scr)
+    launches = sched["folded_launches"] + sched["plain_launches"] + sched["final_copy"]
+    assert launches > 4, sched  # the run is captured, not launched directly
     plan.set_graph(True)
     other = sf.Plan(synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR)
     side = torch.from_numpy(synth.grid_f32((64, 80), stream=7)).to(DEV)
