@@ -552,14 +552,19 @@ def bench_batched(args, default_run=False):
     # the call's arguments marshalled once (ctypes descriptors of 4096 grids);
     # every timed call still runs the whole C entry point
     batch = sf.BatchedRun(handles, datas, scr)
-    log("[bench] persistent + graph, autotuned m (max 2)")
+    log("[bench] persistent + graph, autotuned (fold depth up to 2, strip height, pass cap, "
+        "layout, timed on the whole batch)")
+    t0 = time.perf_counter()
     chosen["tuned"] = batch.run(T, autotune=True, tune_cache=cache, use_graph=True, max_m=2)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    log("[bench]   tuning and first run: %.1f s" % tune_s)
     t_tuned = run_form("persistent_graph_tuned", lambda: batch.run(
         T, tune_cache=cache, use_graph=True, max_m=2), args.steps, args.warmup)
     t_m1 = None
     if args.only_mode != "tuned":
-        log("[bench] persistent + graph, m = 1")
-        t_m1 = run_form("persistent_graph_m1", lambda: batch.run(
+        log("[bench] persistent + graph, default choices (m = 1, 64-row strips, widest layout)")
+        t_m1 = run_form("persistent_graph_default", lambda: batch.run(
             T, use_graph=True, max_m=1), args.steps, args.warmup)
     stream = torch.cuda.current_stream(dev)
 
@@ -628,13 +633,17 @@ def bench_batched(args, default_run=False):
                       "launches + copy back (one hipGraph)")
     roof["launch_unit"] = "one T-step run (all of its launches)"
     roof["passes_per_grid_mean"] = round(sum(passes) / len(passes), 3)
-    # the tuned strip heights per (stencil, radius, size class), from the cache
-    heights = {}
+    # the tuned choices per (stencil, radius, size class), from the cache
+    tuned = {}
     if os.path.exists(cache):
         for line in open(cache):
             f = line.split()
-            if len(f) == 5 and f[0] == "stencil-batched-rows":
-                heights["%s_r%s_class%s" % ("star" if f[1] == "0" else "box", f[2], f[3])] = int(f[4])
+            if len(f) == 5 and f[0].startswith("stencil-batched-"):
+                cls = "%s_r%s_class%s" % ("star" if f[1] == "0" else "box", f[2], f[3])
+                tuned.setdefault(cls, {"m": 1, "rows": 64, "pass_cap": 0, "narrow": 0})
+                fld = {"m": "m", "rows": "rows", "kc": "pass_cap", "narrow": "narrow"}[
+                    f[0][len("stencil-batched-"):]]
+                tuned[cls][fld] = int(f[4])
     res = {
         "metric": METRIC,
         "value": forms["persistent_graph_tuned"]["gstencil_s"],
@@ -647,13 +656,13 @@ def bench_batched(args, default_run=False):
                                "5-point star or 9-point box (random positive weights), FP32, T=50",
                    "points": npts, "T": T,
                    "fold_m_histogram": {str(m): int(sum(1 for x in ms if x == m)) for m in sorted(set(ms))},
-                   "tuned_strip_rows_other_than_64": heights},
+                   "tuned_per_class": tuned, "tuning_wall_s": round(tune_s, 1)},
         "roofline": roof,
         "forms": forms,
         "taps": {"%s_m%d" % ("star" if k == synth.STAR else "box", m): t
                  for (k, m), t in sorted(taps_of.items())},
         "speedup_vs_per_grid_launches": round(t_pg / t_tuned, 2) if t_pg else None,
-        "speedup_tuned_vs_m1": round(t_m1 / t_tuned, 3) if t_m1 else None,
+        "speedup_tuned_vs_default": round(t_m1 / t_tuned, 3) if t_m1 else None,
         "mass_rel_drift_max_64_grids": drift,
         "error_vs_oracle": err,
     }

@@ -313,9 +313,18 @@ int stencil_run_schedule(stencil_plan p, const stencil_grid *g, int64_t T,
  * are copied back into data.  With opts->use_graph the whole time loop is
  * captured once in one hipGraph and replayed on grids[0].stream (all grids
  * must name the same stream).  Every grid needs a caller scratch buffer.
- * The fold depth of each plan is chosen per (stencil, radius, size class) by
- * timing m = 1..opts->max_m on a batch of that class run by these kernels
- * when opts->autotune, else taken from the cache or set to 1; the plans' own
+ * Per (stencil, radius, size class = floor(log2(side))) the library uses a
+ * fold depth m <= opts->max_m, a fused-strip height, a cap on the
+ * applications one fused pass takes (a lower cap narrows the border a strip
+ * discards) and a strip layout (widest strips, or 128- and 64-column ones
+ * only).  With opts->autotune, the classes the cache does not hold are
+ * tuned together on this batch (its shapes and plans, run on scratch copies
+ * of its buffers): coordinate descent from the defaults, each candidate
+ * timed on the whole batch and kept only if the batch runs at least 1%
+ * faster (the evaluation section leaves parameter tuning to future work).
+ * Otherwise the choices come from the cache file, else the defaults (m = 1,
+ * 64 rows, the kernel's cap, widest strips).  Cache lines:
+ * "stencil-batched-{m,rows,kc,narrow} shape r class value".  The plans' own
  * fold depth is not changed.  Results equal the plain canonical-order sweep
  * of the chosen operators bit for bit.  opts may be NULL (no tuning, no
  * graph, m = 1).  The library keeps device tables (and the graph) of the last

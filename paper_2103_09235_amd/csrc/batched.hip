@@ -54,6 +54,7 @@ struct GridInfo {
   // applications spread evenly (the first nfull passes run tail + 1, the
   // others tail); the one-step launches then run the plain remainder only.
   int fpass, nfull, tail;
+  int bord;  // columns a fused strip discards on each side (>= the pass's K*R)
 };
 
 struct Tile {
@@ -130,8 +131,9 @@ k_batched(const Tile *__restrict__ tiles, int ntiles, const GridInfo *__restrict
 // KC its grids take in that pass (blocks of other grids return at once), so
 // a short pass costs its own stages only (a runtime count would make the
 // compiler drain every outstanding load where stage branches merge).
-// Strips keep the KMAX border, so one tiling serves every KC.  Canonical
-// order, bit-identical to KC single applications.
+// A grid's strips keep the border of its largest pass (its fused-step cap,
+// at most KMAX), so one tiling serves every KC it uses.  Canonical order,
+// bit-identical to KC single applications.
 
 // Strip height (rows a fused strip stores): the default, or the
 // STENCIL_BATCH_TB_ROWS override, which also fixes it for the tuner.
@@ -166,7 +168,7 @@ __host__ __device__ constexpr int tb_kmax(int R) { return R == 1 ? 8 : 4; }
 // 64 * VX - B - 2 < nx.
 template <int R, int MASK, int VX, bool VEC, int K>
 __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, int ny, int nx,
-                         int xo0, int y0, int y1, const float *__restrict__ wt) {
+                         int xo0, int y0, int y1, const float *__restrict__ wt, const int B) {
   static_assert(VX >= R && (!VEC || VX == 4), "strip layout");
   using k2d::fmat;
   using k2d::in_mask;
@@ -176,9 +178,8 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
   constexpr int S = 2 * R + 1;
   constexpr int NU = S;
   constexpr int KMAX = tb_kmax(R);
-  constexpr int B = tb_border(KMAX, R);
-  constexpr int WOUT = 64 * VX - 2 * B;
   static_assert(K >= 1 && K <= KMAX, "stages per pass");
+  const int WOUT = 64 * VX - 2 * B;  // B >= K * R: the host's strip plan
   float W[S * S];
 #pragma unroll
   for (int i = 0; i < S * S; ++i) W[i] = wt[i];
@@ -290,9 +291,9 @@ k_batched_tb(const Tile *__restrict__ tiles, const GridInfo *__restrict__ grids,
   float *out = (k & 1) ? g.data : g.scratch;
   const float *w = wtab + g.w_f;
   if (variant_diamond(g.var_f))
-    tb_strip<R, MASK_DIAMOND, VX, VEC, KC>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w);
+    tb_strip<R, MASK_DIAMOND, VX, VEC, KC>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, g.bord);
   else
-    tb_strip<R, MASK_BOX, VX, VEC, KC>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w);
+    tb_strip<R, MASK_BOX, VX, VEC, KC>(in, out, g.ny, g.nx, tl.x0, tl.y0, tl.y1, w, g.bord);
 }
 
 // Strip layouts of the fused passes, and their tile groups: group =
@@ -302,13 +303,13 @@ constexpr int kTbGroups = 2 * kTbLayouts;
 __host__ __device__ constexpr int tb_vx(int layout) {
   return layout == kTb2 ? 2 : layout == kTb1 ? 1 : 4;
 }
-// output columns of a strip: 64 * VX lanes' columns minus the border each side
-__host__ __device__ constexpr int tb_wout(int R, int layout) {
-  return 64 * tb_vx(layout) - 2 * tb_border(tb_kmax(R), R);
+// output columns of a strip: 64 * VX lanes' columns minus the border B each side
+__host__ __device__ constexpr int tb_wout(int B, int layout) {
+  return 64 * tb_vx(layout) - 2 * B;
 }
 // the strip's columns wrap at most once: 64 * VX - B - 2 < nx
-__host__ __device__ constexpr int tb_min_nx(int R, int layout) {
-  return 64 * tb_vx(layout) - tb_border(tb_kmax(R), R) - 1;
+__host__ __device__ constexpr int tb_min_nx(int B, int layout) {
+  return 64 * tb_vx(layout) - B - 1;
 }
 
 // Grids whose total sweep count is odd end in scratch: copy them back.
@@ -332,19 +333,21 @@ k_batched_copyback(const GridInfo *__restrict__ grids, const int *__restrict__ o
   }
 }
 
-// Column strips (layout, first column) of a fused grid: 256-column strips
-// while whole ones fit, then the cheapest cover of the remaining columns:
-// one more wide strip, or 128-column strips followed by 64-column ones,
-// priced by their lanes' columns times a per-layout cost per column (the
-// narrow layouts spend relatively more on neighbour exchange and loop work).
-// Empty when no layout fits the grid's width (then it is not fused).
-std::vector<std::pair<int, int>> strip_plan(int nx, int R, bool vec) {
+// Column strips (layout, first column) of a fused grid with border B:
+// 256-column strips while whole ones fit, then the cheapest cover of the
+// remaining columns: one more wide strip, or 128-column strips followed by
+// 64-column ones, priced by their lanes' columns times a per-layout cost per
+// column (the narrow layouts spend relatively more on neighbour exchange and
+// loop work).  narrow: no 256-column strips where the narrow layouts can
+// cover the grid (more, shorter-lived wavefronts per row band).  Empty when
+// no layout fits the grid's width (then it is not fused).
+std::vector<std::pair<int, int>> strip_plan(int nx, int R, bool vec, int B, bool narrow) {
   constexpr double kCost[kTbLayouts] = {1.0, 1.0, 1.15, 1.4};
   std::vector<std::pair<int, int>> out;
-  const bool ok4 = nx >= tb_min_nx(R, kTb4);
-  const bool ok2 = nx >= tb_min_nx(R, kTb2);
-  const bool ok1 = R == 1 && nx >= tb_min_nx(R, kTb1);
-  const int w4 = tb_wout(R, kTb4), w2 = tb_wout(R, kTb2), w1 = tb_wout(R, kTb1);
+  const bool ok2 = nx >= tb_min_nx(B, kTb2);
+  const bool ok1 = R == 1 && nx >= tb_min_nx(B, kTb1);
+  const bool ok4 = nx >= tb_min_nx(B, kTb4) && !(narrow && (ok2 || ok1));
+  const int w4 = tb_wout(B, kTb4), w2 = tb_wout(B, kTb2), w1 = tb_wout(B, kTb1);
   const int wide = vec ? kTb4Vec : kTb4;
   int x = 0;
   if (ok4)
@@ -390,16 +393,23 @@ struct TuneKey {
   }
 };
 
-// A class's tuned choice: fold depth and fused-strip height (0 = default).
+// A class's tuned choice: fold depth, fused-strip height (0 = default), cap
+// on the applications of one fused pass (0 = the kernel's KMAX; a lower cap
+// narrows the strips' discarded border) and the strip layout (narrow: 128-
+// and 64-column strips only).
 struct TuneVal {
-  int m = 1, rows = 0;
+  int m = 1, rows = 0, kc = 0, narrow = 0;
+  bool operator==(const TuneVal &o) const {
+    return m == o.m && rows == o.rows && kc == o.kc && narrow == o.narrow;
+  }
 };
 
 std::mutex g_mu;
 std::map<std::string, std::map<TuneKey, TuneVal>> g_tune;  // per cache file ("" = memory only)
 
 // Cache file lines: "stencil-batched-m shape r cls m" and, optionally,
-// "stencil-batched-rows shape r cls rows".
+// "stencil-batched-rows shape r cls rows", "stencil-batched-kc shape r cls
+// kc", "stencil-batched-narrow shape r cls 0|1".
 void load_tune_file(const std::string &path, std::map<TuneKey, TuneVal> &out) {
   if (path.empty()) return;
   std::ifstream f(path);
@@ -408,6 +418,8 @@ void load_tune_file(const std::string &path, std::map<TuneKey, TuneVal> &out) {
   while (f >> tag >> shape >> r >> cls >> v) {
     if (tag == "stencil-batched-m") out[TuneKey{shape, r, cls}].m = v;
     if (tag == "stencil-batched-rows") out[TuneKey{shape, r, cls}].rows = std::max(0, v);
+    if (tag == "stencil-batched-kc") out[TuneKey{shape, r, cls}].kc = std::max(0, v);
+    if (tag == "stencil-batched-narrow") out[TuneKey{shape, r, cls}].narrow = v ? 1 : 0;
   }
 }
 
@@ -416,10 +428,13 @@ void save_tune_file(const std::string &path, const std::map<TuneKey, TuneVal> &t
   std::ofstream f(path, std::ios::trunc);
   for (const auto &kv : tab) {
     const TuneKey &k = kv.first;
-    f << "stencil-batched-m " << k.shape << " " << k.r << " " << k.cls << " " << kv.second.m << "\n";
-    if (kv.second.rows)
-      f << "stencil-batched-rows " << k.shape << " " << k.r << " " << k.cls << " " << kv.second.rows
-        << "\n";
+    const TuneVal &v = kv.second;
+    const std::string id = std::to_string(k.shape) + " " + std::to_string(k.r) + " " +
+                           std::to_string(k.cls) + " ";
+    f << "stencil-batched-m " << id << v.m << "\n";
+    if (v.rows) f << "stencil-batched-rows " << id << v.rows << "\n";
+    if (v.kc) f << "stencil-batched-kc " << id << v.kc << "\n";
+    if (v.narrow) f << "stencil-batched-narrow " << id << v.narrow << "\n";
   }
 }
 
@@ -531,8 +546,7 @@ hipError_t enqueue(const BatchEntry &b, hipStream_t s) {
 // Builds a batch: fold weights, fused strips and one-step tiles per grid,
 // device tables, and (use_graph) the captured time loop.
 int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count, int64_t T,
-                const std::vector<int> &m_of, const std::vector<int> &rows_of, bool use_graph,
-                int device, BatchEntry &b) {
+                const std::vector<TuneVal> &cfg, bool use_graph, int device, BatchEntry &b) {
   b.device = device;
   std::vector<GridInfo> gi(count);
   std::vector<float> wt;
@@ -558,7 +572,7 @@ int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count,
   for (int i = 0; i < count; ++i) {
     const stencil_plan p = plans[i];
     const stencil_grid &g = grids[i];
-    const int m = m_of[i];
+    const int m = cfg[i].m;
     GridInfo &G = gi[i];
     G.data = (float *)g.data;
     G.scratch = (float *)g.scratch;
@@ -577,15 +591,19 @@ int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count,
     if (m > 1 && (rc = weights_at(p, m, &G.w_f))) return rc;
     const int R = m * p->r;
     // fused passes: the folded applications (the plain ones at m = 1) of
-    // grids that some strip layout fits, up to tb_kmax(R) per pass
+    // grids that some strip layout fits, up to KM (the class's cap, at most
+    // tb_kmax(R)) per pass; the strips discard a border of KM * R columns
     G.fpass = G.nfull = G.tail = 0;
+    const int KM = R <= kMaxBatchRadius
+                       ? (cfg[i].kc > 0 ? std::min(cfg[i].kc, tb_kmax(R)) : tb_kmax(R)) : 1;
+    G.bord = tb_border(KM, R);
     const std::vector<std::pair<int, int>> strips =
-        R <= kMaxBatchRadius && G.ny >= 2 * tb_kmax(R) * R + 1
-            ? strip_plan(G.nx, R, vx4) : std::vector<std::pair<int, int>>();
+        R <= kMaxBatchRadius && G.ny >= 2 * KM * R + 1
+            ? strip_plan(G.nx, R, vx4, G.bord, cfg[i].narrow != 0)
+            : std::vector<std::pair<int, int>>();
     if (!strips.empty()) {
       const int apps = m > 1 ? G.q : G.s;
       const int rest = m > 1 ? G.s : 0;
-      const int KM = tb_kmax(R);
       if (apps > 1) {
         // the fewest passes, applications spread evenly (pass k takes
         // tail + 1 while k < nfull, else tail).  An odd launch count is not
@@ -604,7 +622,7 @@ int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count,
     if (sweeps % 2) odd.push_back(i);
     if (G.fpass) {
       const int kk = pass_apps(G, 0);
-      const int rows = rows_of[i] > 0 ? rows_of[i] : tb_rows();
+      const int rows = cfg[i].rows > 0 ? cfg[i].rows : tb_rows();
       for (int y0 = 0; y0 < G.ny; y0 += rows)
         for (const auto &st : strips) {
           const int y1 = std::min(G.ny, y0 + rows);
@@ -679,81 +697,122 @@ int build_entry(const stencil_plan *plans, const stencil_grid *grids, int count,
   return STENCIL_OK;
 }
 
-// Time m = 1..max_m for one (stencil, size class) on a batch of grids of
-// the class's side, as the batch runs them (fused strips of the default
-// height, one-step tiles, copy back), over min(T, 64) original steps; the
-// fastest of three runs per m is compared, and a larger m must win by 3%
-// (ties go to the smaller m).  The strip height is not tuned: choices that
-// win for a class alone (a larger m, other heights) measured 8% slower on a
-// mixed batch, whose launches they split; a cache line may still pin one.
-// The tuning batch holds about 2^27 points, enough to fill the GPU in every
-// launch: in a real batch a class shares its launches with the other
-// classes, so its cost is its throughput, not the latency of a launch of its
-// grids alone (which would favour fewer, less efficient launches).
-int tune_batched(stencil_plan p, int side, int max_m, int64_t T, hipStream_t stream, int device,
-                 TuneVal *best_v) {
-  const int64_t pts = (int64_t)side * side;
-  const int cnt = (int)std::max<int64_t>(1, std::min<int64_t>(1 << 15, ((int64_t)1 << 27) / pts));
-  const size_t bytes = (size_t)cnt * pts * sizeof(float);
-  float *a = nullptr, *b = nullptr;
-  STENCIL_HIP_TRY(hipMalloc(&a, bytes));
-  hipError_t e = hipMalloc(&b, bytes);
-  if (e != hipSuccess) {
-    (void)hipFree(a);
-    return hip_fail(e, "tune alloc");
+// The tuner (the paper leaves parameter tuning to future work, evaluation
+// section): every (stencil, radius, size class) of the batch that the cache
+// does not hold gets a fold depth, a fused-strip height, a cap on the
+// applications of a fused pass and a strip layout, chosen by timing the
+// whole batch as it runs (same grids, same plans, every class sharing the
+// launches with the others) on scratch copies of its buffers: a choice that
+// wins for a class alone can lose on the batch by splitting its launches,
+// so only the batch's time decides.  Coordinate descent: from the default
+// (m = 1, 64 rows, the kernel's cap, widest strips), the classes by
+// decreasing share of the batch's points, one parameter at a time over its
+// candidates, a change kept only if the batch runs at least 1% faster (ties
+// keep the earlier choice: smaller m, default height and cap, wide strips).
+// Each timing is the fastest of three runs of min(T, 64) original steps.
+int tune_batch(const stencil_plan *plans, const stencil_grid *grids, int count, int64_t T,
+               int max_m, hipStream_t stream, int device, std::map<TuneKey, TuneVal> &tab,
+               const std::set<TuneKey> &todo) {
+  // scratch copies: every grid's two buffers, 256-byte aligned slices
+  std::vector<size_t> off(count);
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    off[i] = total;
+    total += ((size_t)grids[i].shape[0] * grids[i].shape[1] * sizeof(float) + 255) / 256 * 256;
   }
-  (void)hipMemsetAsync(a, 0, bytes, stream);
-  std::vector<stencil_grid> gs(cnt);
-  std::vector<stencil_plan> ps(cnt, p);
-  for (int i = 0; i < cnt; ++i) {
-    gs[i] = stencil_grid{};
-    gs[i].data = a + (size_t)i * pts;
-    gs[i].scratch = b + (size_t)i * pts;
-    gs[i].dtype = STENCIL_F32;
-    gs[i].dim = 2;
-    gs[i].shape[0] = gs[i].shape[1] = side;
+  char *pool = nullptr;
+  STENCIL_HIP_TRY(hipMalloc(&pool, 2 * total));
+  std::vector<stencil_grid> gs(grids, grids + count);
+  for (int i = 0; i < count; ++i) {
+    gs[i].data = pool + off[i];
+    gs[i].scratch = pool + total + off[i];
     gs[i].stream = stream;
   }
+  hipError_t he = hipMemsetAsync(pool, 0, 2 * total, stream);
   const int64_t Tt = std::min<int64_t>(T, 64);
-  hipEvent_t e0, e1;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
-  double best = 1e30;
-  *best_v = TuneVal();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (he == hipSuccess) he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  std::vector<TuneKey> key_of(count);
+  std::map<TuneKey, double> share;
+  for (int i = 0; i < count; ++i) {
+    const stencil_plan p = plans[i];
+    key_of[i] = TuneKey{p->shape, p->r, size_class(std::min(grids[i].shape[0], grids[i].shape[1]))};
+    share[key_of[i]] += (double)grids[i].shape[0] * grids[i].shape[1];
+  }
+  std::map<TuneKey, TuneVal> cur = tab;
+  for (const TuneKey &k : todo) cur[k] = TuneVal();
   int rc = STENCIL_OK;
-  for (int m = 1; m <= max_m && rc == STENCIL_OK; ++m) {
-    const int rows = 0;  // the default height
-    if (m * p->r > kMaxBatchRadius || side < 2 * m * p->r + 1) break;
+  // the batch's time with the choices in `c` (ms), or a negative value for a
+  // configuration the grids do not admit
+  auto time_with = [&](const std::map<TuneKey, TuneVal> &c, double *ms_out) -> int {
+    std::vector<TuneVal> cfg(count);
+    for (int i = 0; i < count; ++i) {
+      cfg[i] = c.at(key_of[i]);
+      const int64_t side = std::min(grids[i].shape[0], grids[i].shape[1]);
+      const int r = plans[i]->r;
+      if (cfg[i].m * r > kMaxBatchRadius || 2 * cfg[i].m * r + 1 > side) {
+        *ms_out = -1.0;
+        return STENCIL_OK;
+      }
+    }
     BatchEntry be;
-    rc = build_entry(ps.data(), gs.data(), cnt, Tt, std::vector<int>(cnt, m),
-                     std::vector<int>(cnt, rows), false, device, be);
-    if (rc) break;
-    float ms = 1e30f;
-    hipError_t he = enqueue(be, stream);  // warm
-    for (int rep = 0; rep < 3 && he == hipSuccess; ++rep) {
-      (void)hipEventRecord(e0, stream);
-      he = enqueue(be, stream);
-      (void)hipEventRecord(e1, stream);
-      if (he == hipSuccess) he = hipEventSynchronize(e1);
+    int rc2 = build_entry(plans, gs.data(), count, Tt, cfg, false, device, be);
+    if (rc2) return rc2;
+    float best = 1e30f;
+    hipError_t e = enqueue(be, stream);  // warm
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+      e = hipEventRecord(e0, stream);
+      if (e == hipSuccess) e = enqueue(be, stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
       float t = 0.f;
-      (void)hipEventElapsedTime(&t, e0, e1);
-      ms = std::min(ms, t);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      best = std::min(best, t);
     }
     free_entry(be);
-    if (he != hipSuccess) {
-      rc = hip_fail(he, "tune run");
-      break;
-    }
-    if (ms < best * 0.97) {  // 3% margin, ties to smaller m
-      best = ms;
-      best_v->m = m;
+    if (e != hipSuccess) return hip_fail(e, "batched tuning run");
+    *ms_out = best;
+    return STENCIL_OK;
+  };
+  double best_ms = 0.0;
+  if (he != hipSuccess) rc = hip_fail(he, "batched tuning setup");
+  if (rc == STENCIL_OK) rc = time_with(cur, &best_ms);
+  std::vector<TuneKey> order(todo.begin(), todo.end());
+  std::stable_sort(order.begin(), order.end(),
+                   [&](const TuneKey &a, const TuneKey &b) { return share[a] > share[b]; });
+  for (const TuneKey &k : order) {
+    if (rc != STENCIL_OK || best_ms <= 0.0) break;
+    const int kmax = tb_kmax(std::min(k.r, kMaxBatchRadius));
+    for (int param = 0; param < 4 && rc == STENCIL_OK; ++param) {
+      std::vector<int> cands;
+      if (param == 0)
+        for (int m = 1; m <= max_m && m * k.r <= kMaxBatchRadius; ++m) cands.push_back(m);
+      if (param == 1) cands = {0, kmax / 2};
+      if (param == 2) cands = {0, 32, 128, 256};
+      if (param == 3) cands = {0, 1};
+      for (int v : cands) {
+        std::map<TuneKey, TuneVal> trial = cur;
+        TuneVal &tv = trial[k];
+        int *field = param == 0 ? &tv.m : param == 1 ? &tv.kc : param == 2 ? &tv.rows : &tv.narrow;
+        if (*field == v) continue;
+        *field = v;
+        double ms = 0.0;
+        rc = time_with(trial, &ms);
+        if (rc != STENCIL_OK) break;
+        if (ms > 0.0 && ms < best_ms * 0.99) {
+          best_ms = ms;
+          cur = trial;
+        }
+      }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(stream);
-  (void)hipFree(a);
-  (void)hipFree(b);
+  (void)hipFree(pool);
+  if (rc == STENCIL_OK)
+    for (const TuneKey &k : todo) tab[k] = cur[k];
   return rc;
 }
 
@@ -814,39 +873,40 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
   STENCIL_HIP_TRY(hipGetDevice(&device));
   std::lock_guard<std::mutex> lock(g_mu);
 
-  // --- fold depth and strip height per grid: tuned per (shape, r, size
-  // class), cached
+  // --- fold depth, strip height, pass cap and strip layout per grid: tuned
+  // per (shape, r, size class) on the whole batch, cached
   std::map<TuneKey, TuneVal> &tab = g_tune[cache_path];
   if (tab.empty()) load_tune_file(cache_path, tab);
-  std::vector<int> m_of(count, 1), rows_of(count, 0);
-  bool tuned_any = false;
+  std::set<TuneKey> todo;
+  for (int i = 0; i < count; ++i) {
+    const stencil_plan p = plans[i];
+    const TuneKey key{p->shape, p->r, size_class(std::min(grids[i].shape[0], grids[i].shape[1]))};
+    if (!tab.count(key)) todo.insert(key);
+  }
+  if (autotune && !todo.empty()) {
+    if (int rc = tune_batch(plans, grids, count, T, max_m, stream, device, tab, todo)) return rc;
+    save_tune_file(cache_path, tab);
+  }
+  std::vector<TuneVal> cfg(count);
   for (int i = 0; i < count; ++i) {
     const stencil_plan p = plans[i];
     const int64_t side = std::min(grids[i].shape[0], grids[i].shape[1]);
     const TuneKey key{p->shape, p->r, size_class(side)};
-    TuneVal v;
     auto it = tab.find(key);
-    if (it != tab.end()) {
-      v = it->second;
-    } else if (autotune) {
-      // this grid's side represents its class
-      int rc = tune_batched(p, (int)std::min<int64_t>(side, 1 << 12), max_m, T, stream, device, &v);
-      if (rc) return rc;
-      tab[key] = v;
-      tuned_any = true;
-    }
+    TuneVal v = it != tab.end() ? it->second : TuneVal();
     int m = std::max(1, std::min(v.m, max_m));
     while (m > 1 && (m * p->r > kMaxBatchRadius || 2 * m * p->r + 1 > side)) --m;
-    m_of[i] = m;
-    rows_of[i] = tb_rows_env() ? 0 : std::max(0, std::min(v.rows, 1 << 16));
+    v.m = m;
+    v.rows = tb_rows_env() ? 0 : std::max(0, std::min(v.rows, 1 << 16));
+    v.kc = std::max(0, std::min(v.kc, 64));
+    cfg[i] = v;
   }
-  if (tuned_any) save_tune_file(cache_path, tab);
   if (opts && opts->chosen_m)
-    for (int i = 0; i < count; ++i) opts->chosen_m[i] = m_of[i];
+    for (int i = 0; i < count; ++i) opts->chosen_m[i] = cfg[i].m;
 
   // --- signature of this batch (pointers, sizes, plans, fold depths, T)
   std::vector<uint64_t> key;
-  key.reserve(4 + 6 * (size_t)count);  // (fold depth | strip height << 32) per grid
+  key.reserve(4 + 6 * (size_t)count);
   key.push_back((uint64_t)device);
   key.push_back((uint64_t)T);
   key.push_back(use_graph ? 1 : 0);
@@ -857,14 +917,16 @@ extern "C" int stencil_run_batched(const stencil_plan *plans, stencil_grid *grid
     key.push_back((uint64_t)(uintptr_t)grids[i].scratch);
     key.push_back((uint64_t)grids[i].shape[0]);
     key.push_back((uint64_t)grids[i].shape[1]);
-    key.push_back((uint64_t)m_of[i] | ((uint64_t)rows_of[i] << 32));
+    // the grid's choices: fold depth | pass cap << 8 | narrow << 16 | height << 32
+    key.push_back((uint64_t)cfg[i].m | ((uint64_t)cfg[i].kc << 8) |
+                  ((uint64_t)cfg[i].narrow << 16) | ((uint64_t)cfg[i].rows << 32));
   }
   auto hit = std::find_if(g_cache.begin(), g_cache.end(),
                           [&](const BatchEntry &b) { return b.key == key; });
   if (hit == g_cache.end()) {
     BatchEntry b;
     b.key = key;
-    if (int rc = build_entry(plans, grids, count, T, m_of, rows_of, use_graph, device, b))
+    if (int rc = build_entry(plans, grids, count, T, cfg, use_graph, device, b))
       return rc;
     g_cache.push_front(b);
     if (g_cache.size() > kCacheEntries) {

@@ -776,24 +776,34 @@ NARROW_SHAPES = [(70, 55), (64, 54), (100, 119), (81, 118), (90, 247), (65, 246)
                  (33, 700), (17, 200), (16, 300), (257, 301), (120, 252), (96, 480), (50, 484)]
 
 
-@pytest.mark.parametrize("T,m,rows", [(50, 1, 0), (21, 2, 0), (13, 1, 32), (15, 2, 128),
-                                      (9, 1, 16)])
-def test_batched_narrow_strips_bit_exact(tmp_path, T, m, rows):
+@pytest.mark.parametrize("T,m,rows,kc,narrow", [
+    (50, 1, 0, 0, 0), (21, 2, 0, 0, 0), (13, 1, 32, 0, 0), (15, 2, 128, 0, 0), (9, 1, 16, 0, 0),
+    # tuned caps on the applications of a fused pass (narrower borders) and
+    # the narrow strip layout
+    (17, 1, 0, 4, 0), (23, 1, 32, 2, 1), (19, 2, 0, 2, 1), (11, 1, 128, 3, 1), (26, 1, 0, 0, 1)])
+def test_batched_narrow_strips_bit_exact(tmp_path, T, m, rows, kc, narrow):
     """Fused passes cover a grid's columns with 256-column strips and its
     last columns (or a whole narrow grid) with 128- and 64-column strips, of
-    the tuned height (rows; 0 = the default 64); grids no layout fits run one
-    step per launch.  Every grid bit-exact against the oracle's mirror, stars
-    and boxes, rows of whole vectors or not."""
+    the tuned height (rows; 0 = the default 64), the tuned cap on a pass's
+    applications (kc; 0 = the kernel's 8 at radius 1, 4 at radius 2) and
+    layout (narrow: no 256-column strips); grids no layout fits run one step
+    per launch.  Every grid bit-exact against the oracle's mirror, stars and
+    boxes, rows of whole vectors or not."""
     kinds = [synth.STAR if i % 2 == 0 else synth.BOX for i in range(len(NARROW_SHAPES))]
     weights = [synth.WORKLOADS["star2d"].weights if k == synth.STAR
                else synth.WORKLOADS["box2d"].weights for k in kinds]
     grids = [synth.grid_f32(sh, stream=5 + i % 10) for i, sh in enumerate(NARROW_SHAPES)]
-    print("batched narrow strips T", T, "m", m, "rows", rows, NARROW_SHAPES, flush=True)
+    print("batched narrow strips T", T, "m", m, "rows", rows, "kc", kc, "narrow", narrow,
+          NARROW_SHAPES, flush=True)
     cache = tmp_path / "m.txt"
-    cache.write_text("".join("stencil-batched-m %d 1 %d %d\n" % (sh, c, m)
-                             for sh in (0, 1) for c in range(3, 12)) +
+    cls = [(sh, c) for sh in (0, 1) for c in range(3, 12)]
+    cache.write_text("".join("stencil-batched-m %d 1 %d %d\n" % (sh, c, m) for sh, c in cls) +
                      "".join("stencil-batched-rows %d 1 %d %d\n" % (sh, c, rows)
-                             for sh in (0, 1) for c in range(3, 12) if rows))
+                             for sh, c in cls if rows) +
+                     "".join("stencil-batched-kc %d 1 %d %d\n" % (sh, c, kc)
+                             for sh, c in cls if kc) +
+                     "".join("stencil-batched-narrow %d 1 %d 1\n" % (sh, c)
+                             for sh, c in cls if narrow))
     outs, chosen = _run_batched(kinds, weights, grids, T, tune_cache=str(cache), max_m=m)
     assert chosen == [m] * len(grids)
     for g, w, o, sh in zip(grids, weights, outs, NARROW_SHAPES):
