@@ -115,6 +115,7 @@ KERNEL_SOURCES = {
                 "sweep2d_r5.hip", "sweep2d_r6.hip", "sweep2d_r7.hip", "sweep2d_r8.hip"),
     "sweep2dtb": ("sweep2d_tb.hip", "sweep2d_common.h"),
     "sweep3d": ("sweep3d.hip",),
+    "sweep3dtb": ("sweep3d_tb.hip",),
     "mfma2d": ("mfma2d.hip",),
     "batched": ("batched.hip", "sweep2d_common.h", "sweep2d_impl.h"),
 }
@@ -444,7 +445,7 @@ def bench_grid(args, wl_name, default_run=False):
                                         "78.6 TFLOP/s (FMAs, packed FP32 not used)")
     if mode_name.startswith("mfma"):
         roof["mfma_issued_frac_of_bf16_peak"] = forms[key]["mfma_issued_frac_of_bf16_peak"]
-    fused = per_launch > 1 and wl.dim == 2
+    fused = per_launch > 1 and wl.dim in (2, 3)
     tkey = {"vector": ("sweep%dd%s_m%d" % (wl.dim, "tb" if fused else "", m)),
             "vector_graph": ("sweep%dd%s_m%d" % (wl.dim, "tb" if fused else "", m)),
             "vector_unfused": "sweep%dd_m%d" % (wl.dim, m),
@@ -453,8 +454,8 @@ def bench_grid(args, wl_name, default_run=False):
             "mfma_bf16x3": "mfma2d_m%d" % m}[mode_name]
     roof["traffic"] = traffic_from_profiles(tkey, wl_name)
     roof["kernel"] = "%s R=%d (%s, %d taps, %.2f applications per launch)" % (
-        "k_sweep2d_tb" if fused else ("k_mfma2d" if mode_name.startswith("mfma")
-                                      else "k_sweep%dd" % wl.dim),
+        ("k_sweep%dd_tb" % wl.dim) if fused else ("k_mfma2d" if mode_name.startswith("mfma")
+                                                  else "k_sweep%dd" % wl.dim),
         m * r, mode_name, taps, per_launch)
     roof["flops_basis"] = ("2 x FMAs per point (dense taps; 2 x rank x (2R+1) for the separable "
                            "form) x points x applications per launch")

@@ -208,7 +208,7 @@ hipError_t dispatch(stencil_plan p, const SweepLaunch &L) {
     Ls.sep = p->mode == STENCIL_MODE_SEPARABLE;
     e = L.steps > 1 ? launch_sweep2d_tb(Ls) : launch_sweep2d(Ls);
   }
-  else e = launch_sweep3d(L);
+  else e = L.steps > 1 ? launch_sweep3d_tb(L) : launch_sweep3d(L);
   if (e == hipErrorNotSupported) {
     // the generic kernel neither fuses steps nor applies a floor
     if (L.steps != 1 || L.floor) return hipErrorNotSupported;
@@ -580,7 +580,7 @@ int check_run(stencil_plan p, const stencil_grid *g, int64_t T, Geom &geo) {
 
 // The launches of a run: floor(T/m) applications of the folded operator,
 // then T mod m of the plain one.  Tiled kernels may fuse several
-// applications of one operator per launch (1D and 2D temporal blocking);
+// applications of one operator per launch (1D, 2D and 3D temporal blocking);
 // the 2D fused kernel needs 16-byte aligned buffers (a plan-owned scratch
 // buffer always is).  An odd launch total leaves the result in scratch and
 // costs a final copy, unless a fusing pass can split once more.
@@ -646,6 +646,8 @@ Schedule make_schedule(stencil_plan p, const Geom &geo, int dtype, const void *d
       kmax[i] = std::max(1, sweep1d_max_steps(L));
     else if (p->dim == 2 && p->mode == STENCIL_MODE_VECTOR && aligned)
       kmax[i] = std::max(1, sweep2d_max_steps(L));
+    else if (p->dim == 3 && p->mode == STENCIL_MODE_VECTOR)
+      kmax[i] = std::max(1, sweep3d_max_steps(L));
     if (p->max_fuse > 0) kmax[i] = std::min<int64_t>(kmax[i], p->max_fuse);
     sc.launches[i] = (sc.apps[i] + kmax[i] - 1) / kmax[i];
   }

@@ -163,6 +163,10 @@ int sweep1d_max_steps(const SweepLaunch &L);
 // the launch of 2 <= L.steps <= that many steps.
 int sweep2d_max_steps(const SweepLaunch &L);
 hipError_t launch_sweep2d_tb(const SweepLaunch &L);
+// 3D FP32 temporal blocking: the most applications one launch fuses (1 =
+// none), and the launch of 2 <= L.steps <= that many.
+int sweep3d_max_steps(const SweepLaunch &L);
+hipError_t launch_sweep3d_tb(const SweepLaunch &L);
 
 // Zero-boundary runs (dirichlet.hip).  Padded arrays have extents np, the
 // interior starting at off with extents n (z, y, x).

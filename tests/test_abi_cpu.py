@@ -228,7 +228,7 @@ def test_run_schedule_counts_launches():
     # modes other than VECTOR run one application per launch in 2D
     star.set_mode(sf.STENCIL_MODE_SYMMETRIC)
     assert _sched(star, (8192, 8192), 1000)["plain_launches"] == 1000
-    # 1D fuses many steps per launch; 3D none
+    # 1D fuses many steps per launch
     heat = sf.Plan(synth.heat1d_weights(), sf.STENCIL_STAR)
     assert _sched(heat, (1_000_000,), 100, sf.STENCIL_F64)["plain_launches"] < 10
     # short lines: wavefront spans of 1024 points, at most 51 steps per launch
@@ -239,9 +239,19 @@ def test_run_schedule_counts_launches():
     assert _sched(heat, (20_000_000,), 200, sf.STENCIL_F64)["plain_launches"] == 2
     box5 = sf.Plan(synth.WORKLOADS["box1d5p"].weights, sf.STENCIL_BOX)
     assert _sched(box5, (10_240_000,), 1000, sf.STENCIL_F64)["plain_launches"] == 20
+    # 3D FP32: the 27-point box two steps per launch (5 -> 3 launches, one
+    # more for an even count), the 7-point star four; FP64 grids one; a
+    # z-axis shorter than 2KR+1 planes takes fewer steps per launch
     box3 = sf.Plan(np.ones((3, 3, 3)) / 27, sf.STENCIL_BOX)
     s = _sched(box3, (64, 64, 64), 5)
-    assert (s["plain_launches"], s["final_copy"]) == (5, True)
+    assert (s["plain_launches"], s["final_copy"]) == (4, False)
+    star3 = sf.Plan(synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR)
+    s = _sched(star3, (512, 512, 512), 200)
+    assert (s["plain_launches"], s["final_copy"]) == (50, False)
+    assert _sched(star3, (512, 512, 512), 200, sf.STENCIL_F64)["plain_launches"] == 200
+    assert _sched(star3, (8, 512, 512), 8)["plain_launches"] == 4  # three per launch at most
+    assert _sched(star3, (4, 512, 512), 4)["plain_launches"] == 4  # one per launch
+    # (folded plans need the GPU to fold: the GPU tests cover them)
     with pytest.raises(sf.StencilError) as e:
         _sched(star, (8192, 8192), -1)
     assert e.value.code == sf.STENCIL_E_ARG

@@ -448,6 +448,57 @@ def test_temporal_blocking_bit_exact(case):
     assert np.array_equal(outs[1], ref)
 
 
+TB3_CASES = [
+    # (name, weights, kind, shape, T, m, fusion); shapes span several 64 x TY
+    # tiles and z-segments with ragged edges, rows of whole vectors or not
+    ("star3d_k4", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (40, 48, 192), 8, 1, 0),
+    ("star3d_k3k2_ragged", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (37, 41, 130), 9, 1,
+     0),
+    ("star3d_k3", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (33, 35, 68), 7, 1, 3),
+    ("star3d_k2", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (30, 70, 136), 6, 1, 2),
+    ("box3d_k2", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (36, 40, 132), 5, 1, 0),
+    ("box3d_k2_ragged", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (20, 33, 70), 4, 1, 0),
+    ("star3d_m2_fused", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (40, 36, 100), 9, 2, 0),
+    ("box3d_m2_not_fused", synth.WORKLOADS["box3d"].weights, sf.STENCIL_BOX, (24, 30, 68), 6, 2, 0),
+    # tiles wider than the grid: every run wraps several times
+    ("star3d_k4_tiny", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (9, 7, 6), 8, 1, 0),
+    ("star3d_k4_narrow_vec", synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR, (12, 10, 8), 8, 1,
+     0),
+]
+
+
+@pytest.mark.parametrize("case", TB3_CASES, ids=lambda c: c[0])
+def test_temporal_blocking_3d_bit_exact(case):
+    """3D: K applications per launch streamed through K pipeline stages in
+    LDS equal K single-step launches bit for bit (the oracle's FP32 mirror
+    of the schedule, and the same plan unfused)."""
+    name, w, kind, shape, T, m, fusion = case
+    w = synth.to_f32_exact(w)
+    u0 = synth.grid_f32(shape)
+    print("3D temporal blocking", name, shape, "T", T, "m", m, "fusion", fusion, flush=True)
+    outs = []
+    for fz in (fusion, 1):
+        plan = sf.Plan(w, kind)
+        if m > 1:
+            plan.fold(m)
+        plan.set_fusion(fz)
+        data = torch.from_numpy(u0).to(DEV)
+        scr = torch.empty_like(data)
+        sched = plan.schedule(data, T, scr)
+        plan.run(data, T, scr)
+        torch.cuda.synchronize()
+        outs.append((data.cpu().numpy(), sched))
+        plan.close()
+    ref = oracle.folded_reference_f32(w, u0, T, m)
+    assert np.array_equal(outs[0][0], ref)
+    assert np.array_equal(outs[1][0], ref)
+    fused = outs[0][1]
+    if not name.endswith("not_fused"):
+        launches = fused["folded_launches"] if m > 1 else fused["plain_launches"]
+        apps = fused["folded_apps"] if m > 1 else fused["plain_apps"]
+        assert launches < apps, fused  # several applications per launch
+
+
 def test_run_schedule_folded_then_plain():
     """floor(T/m) applications of W_m (radius 4: two per launch), then the
     T mod m plain ones; the reported plan is the one stencil_run follows
