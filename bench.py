@@ -21,8 +21,9 @@ weights prepared beforehand and the grid resident in HBM.
 
 The line's top-level fields describe star2d's fastest form; "configs" holds
 the same fields for every workload.  --workload X runs one workload alone
-(profiling runs), and also the Table 1 extras (box1d5p, apop1d, life2d,
-unitbox2d, star2d_dirichlet).
+(profiling runs), and also the extras: Table 1's box1d5p, apop1d and
+life2d, the unit box unitbox2d, the zero-boundary star2d_dirichlet and the
+FP64 star star2d_f64.
 
 Prints ONE JSON line on stdout.
 """
@@ -72,7 +73,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="all",
                     choices=["all", "star2d", "heat1d", "star3d", "box3d", "box2d", "unitbox2d",
-                             "star2d_dirichlet", "box1d5p", "apop1d", "life2d", "batched"])
+                             "star2d_dirichlet", "star2d_f64", "box1d5p", "apop1d", "life2d",
+                             "batched"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the FP64 oracle reference (profiling runs)")
@@ -322,7 +324,7 @@ def bench_grid(args, wl_name, default_run=False):
             if not zero_bc:
                 # the same launches captured once in a hipGraph and replayed
                 form_modes.append(("vector_graph", sf.STENCIL_MODE_VECTOR, 0))
-            if wl.dim == 2 and f32 and not zero_bc:
+            if wl.dim in (2, 3) and not zero_bc:
                 form_modes.append(("vector_unfused", sf.STENCIL_MODE_VECTOR, 1))
         if symmetric:
             form_modes.append(("symmetric", sf.STENCIL_MODE_SYMMETRIC, 0))

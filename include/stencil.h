@@ -154,11 +154,13 @@ int stencil_plan_set_mode(stencil_plan p, int mode);
 /*
  * stencil_plan_set_fusion -- the most operator applications one launch may
  * fuse (temporal blocking: Section 3.4 keeps several time steps of a tile on
- * chip between loads).  The 1D kernels and the 2D FP32 VECTOR kernels
- * (radius 1-4, rows of whole 16-byte vectors, at least 256 columns) fuse
- * steps in registers; either way the result equals one launch per
- * application bit for bit.  0 = the library's choice
- * (default), 1 = one application per launch, k > 1 = at most k.
+ * chip between loads).  The 1D kernels and the 2D VECTOR kernels (FP32
+ * radius 1-4, FP64 radius 1-2; rows of whole 16-byte vectors, at least 256
+ * columns) fuse steps in registers; the 3D FP32 VECTOR kernels (the radius-1
+ * star up to 4 steps, the radius-1 box 2, the folded star of radius 2 two
+ * applications) stream them through LDS pipeline stages.  Either way the
+ * result equals one launch per application bit for bit.  0 = the library's
+ * choice (default), 1 = one application per launch, k > 1 = at most k.
  * Errors: E_ARG.  No device work.
  */
 int stencil_plan_set_fusion(stencil_plan p, int max_steps);
@@ -278,8 +280,8 @@ int stencil_profitability(stencil_plan p, int m, int64_t *naive,
  * Dirichlet (STENCIL_DIRICHLET) runs copy the grid into plan-owned buffers
  * padded by m*r on each face, the pad holding the ghost value (four padded
  * grids, kept for later runs), run each application there and copy the
- * result back; g->scratch is not used.  Plain applications of 2D FP32
- * VECTOR plans and of 1D plans (every mode but EXACT_ORDER) fuse several per
+ * result back; g->scratch is not used.  Plain applications of 2D VECTOR
+ * plans and of 1D plans (every mode but EXACT_ORDER) fuse several per
  * launch, the fused kernels writing the ghost value outside the grid after
  * every step; folded applications run one per launch.
  * Enqueued asynchronously on g->stream; the caller keeps data and scratch

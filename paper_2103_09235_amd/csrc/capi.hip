@@ -629,11 +629,11 @@ Schedule make_schedule(stencil_plan p, const Geom &geo, int dtype, const void *d
     L.dtype = dtype;
     L.op = &op;
     if (p->boundary != STENCIL_PERIODIC) {
-      // plain applications of 2D FP32 VECTOR plans and of 1D plans (not
+      // plain applications of 2D VECTOR plans and of 1D plans (not
       // EXACT_ORDER) fuse on the padded grid, each step writing the ghost
       // value outside the interior; folded ones restore the pad one by one
       kmax[i] = 1;
-      if (i == 1 && p->dim == 2 && dtype == STENCIL_F32 && p->mode == STENCIL_MODE_VECTOR) {
+      if (i == 1 && p->dim == 2 && p->mode == STENCIL_MODE_VECTOR) {
         int64_t np[3], off[3];
         L.g = padded_geom(p, geo, dtype, np, off);
         kmax[i] = std::max(1, sweep2d_max_steps(L));

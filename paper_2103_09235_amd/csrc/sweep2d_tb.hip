@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <utility>
 
 #include "internal.h"
 #include "sweep2d_common.h"
@@ -65,13 +66,26 @@ __device__ __forceinline__ float lane_from_right(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
                                                                 0x130, 0xF, 0xF, true));
 }
+// FP64: the two 32-bit halves moved by the same shifts
+__device__ __forceinline__ double lane_from_left(double x) {
+  const int2 h = __builtin_bit_cast(int2, x);
+  return __builtin_bit_cast(double, make_int2(
+      __builtin_amdgcn_update_dpp(0, h.x, 0x138, 0xF, 0xF, true),
+      __builtin_amdgcn_update_dpp(0, h.y, 0x138, 0xF, 0xF, true)));
+}
+__device__ __forceinline__ double lane_from_right(double x) {
+  const int2 h = __builtin_bit_cast(int2, x);
+  return __builtin_bit_cast(double, make_int2(
+      __builtin_amdgcn_update_dpp(0, h.x, 0x130, 0xF, 0xF, true),
+      __builtin_amdgcn_update_dpp(0, h.y, 0x130, 0xF, 0xF, true)));
+}
 
 // One strip (tile t).  ZB: zero every stage's output outside zbox.
-template <int R, int MASK, int K, bool ZB>
-__device__ __forceinline__ void tb_body(const float *__restrict__ in, float *__restrict__ out,
+template <typename T, int R, int MASK, int K, bool ZB>
+__device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict__ out,
                                         int ny, int nx, int BY, int tiles_x,
-                                        const WArr<float, (2 * R + 1) * (2 * R + 1)> &W,
-                                        int4 zbox, float zval, int t) {
+                                        const WArr<T, (2 * R + 1) * (2 * R + 1)> &W,
+                                        int4 zbox, T zval, int t) {
   constexpr int S = 2 * R + 1;
   constexpr int NU = S;                        // queue length = unroll of the row loop
   constexpr int B = border(K, R);
@@ -100,17 +114,17 @@ __device__ __forceinline__ void tb_body(const float *__restrict__ in, float *__r
   // most strips hold no pad column: their rows are masked whole (uniform)
   const bool cols_in = !ZB || (xi0 >= zbox.z && xi0 + kSpan <= zbox.w);
 
-  float acc[K][NU][kVX];
+  T acc[K][NU][kVX];
 #pragma unroll
   for (int s = 0; s < K; ++s)
 #pragma unroll
     for (int k = 0; k < NU; ++k)
 #pragma unroll
-      for (int v = 0; v < kVX; ++v) acc[s][k][v] = 0.0f;
+      for (int v = 0; v < kVX; ++v) acc[s][k][v] = T(0);
 
   // One level-0 row j through the K stages; u = (j - jstart) mod NU.
-  auto row = [&](const int j, const int u, const float (&in_row)[kVX]) {
-    float cur[kVX];
+  auto row = [&](const int j, const int u, const T (&in_row)[kVX]) {
+    T cur[kVX];
 #pragma unroll
     for (int v = 0; v < kVX; ++v) cur[v] = in_row[v];
     // Stage s takes level-s row j - s*R and finishes level-(s+1) row
@@ -118,7 +132,7 @@ __device__ __forceinline__ void tb_body(const float *__restrict__ in, float *__r
 #pragma unroll
     for (int s = 0; s < K; ++s) {
       // the R columns on either side come from the neighbouring lanes
-      float win[kVX + 2 * R];
+      T win[kVX + 2 * R];
 #pragma unroll
       for (int i = 0; i < R; ++i) win[i] = lane_from_left(cur[kVX - R + i]);
 #pragma unroll
@@ -135,11 +149,11 @@ __device__ __forceinline__ void tb_body(const float *__restrict__ in, float *__r
 #pragma unroll
         for (int ox = -R; ox <= R; ++ox) {
           if (in_mask<MASK, R>(oy, ox)) {
-            const float wt = W[(oy + R) * S + (ox + R)];
+            const T wt = W[(oy + R) * S + (ox + R)];
             const bool first = k == S - 1 && ox == (MASK == MASK_BOX ? -R : 0);
 #pragma unroll
             for (int v = 0; v < kVX; ++v)
-              acc[s][slot][v] = fmat(wt, win[R + v + ox], first ? 0.0f : acc[s][slot][v]);
+              acc[s][slot][v] = fmat(wt, win[R + v + ox], first ? T(0) : acc[s][slot][v]);
           }
         }
       }
@@ -156,7 +170,7 @@ __device__ __forceinline__ void tb_body(const float *__restrict__ in, float *__r
       }
     }
     const int yd = j - K * R;  // level-K row just completed
-    if (store_ok && yd >= y0 && yd < y1) store_vec<float, kVX>(out + (size_t)yd * nx + xo0 + lo, cur);
+    if (store_ok && yd >= y0 && yd < y1) store_vec<T, kVX>(out + (size_t)yd * nx + xo0 + lo, cur);
   };
 
   // Level-0 rows arrive a group of NU rows ahead: a group's loads are issued
@@ -165,12 +179,12 @@ __device__ __forceinline__ void tb_body(const float *__restrict__ in, float *__r
   // alternate, so no register with a load in flight is ever copied (a copy
   // makes the compiler wait for every outstanding access), and the loads are
   // unconditional for the same reason: rows past the end re-read the last.
-  auto fetch = [&](const int j0, float (&buf)[NU][kVX]) {
+  auto fetch = [&](const int j0, T (&buf)[NU][kVX]) {
 #pragma unroll
     for (int p = 0; p < NU; ++p)
-      load_vec<float, kVX>(in + (size_t)wrap1(min(j0 + p, jend - 1), ny) * nx + gx, buf[p]);
+      load_vec<T, kVX>(in + (size_t)wrap1(min(j0 + p, jend - 1), ny) * nx + gx, buf[p]);
   };
-  float bufA[NU][kVX], bufB[NU][kVX];
+  T bufA[NU][kVX], bufB[NU][kVX];
   fetch(jstart, bufA);
   // Pairs of NU-row groups: up to 2NU-1 rows past jend are computed and
   // dropped.
@@ -188,12 +202,12 @@ __device__ __forceinline__ void tb_body(const float *__restrict__ in, float *__r
 // the launch lasts as long as its slowest strip: a zero-boundary launch runs
 // the masked body in every strip (an unmasked body for the strips that hold
 // no pad cell measured no faster).
-template <int R, int MASK, int K, bool ZB>
+template <typename T, int R, int MASK, int K, bool ZB>
 __global__ void __launch_bounds__(64)
-k_sweep2d_tb(const float *__restrict__ in, float *__restrict__ out, int ny, int nx, int BY,
-             int tiles_x, WArr<float, (2 * R + 1) * (2 * R + 1)> W, int4 zbox, float zval) {
-  tb_body<R, MASK, K, ZB>(in, out, ny, nx, BY, tiles_x, W, zbox, zval,
-                          xcd_contiguous(blockIdx.x, gridDim.x));
+k_sweep2d_tb(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
+             int tiles_x, WArr<T, (2 * R + 1) * (2 * R + 1)> W, int4 zbox, T zval) {
+  tb_body<T, R, MASK, K, ZB>(in, out, ny, nx, BY, tiles_x, W, zbox, zval,
+                             xcd_contiguous(blockIdx.x, gridDim.x));
 }
 
 // Wavefront slots the device holds at once for a kernel (one wave per block).
@@ -209,15 +223,15 @@ int resident_blocks(F kernel) {
   return std::max(1, cus * per_cu);
 }
 
-template <int R, int MASK, int K>
+template <typename T, int R, int MASK, int K>
 hipError_t launch_one(const SweepLaunch &L) {
   if (L.zb && (L.zbox[0] < R || L.zbox[2] < R || (int)L.g.ny - L.zbox[1] < R ||
                (int)L.g.nx - L.zbox[3] < R))
     return hipErrorInvalidValue;  // the pad must hold every read of the interior
   constexpr int S = 2 * R + 1;
   constexpr int WOUT = kSpan - 2 * border(K, R);
-  WArr<float, S * S> W;
-  for (int i = 0; i < S * S; ++i) W.v[i] = L.op->w32[i];
+  WArr<T, S * S> W;
+  for (int i = 0; i < S * S; ++i) W.v[i] = sizeof(T) == 4 ? (T)L.op->w32[i] : (T)L.op->w64[i];
   const int ny = (int)L.g.ny, nx = (int)L.g.nx;
   const int tiles_x = (nx + WOUT - 1) / WOUT;
   static const int env_by = [] {
@@ -229,7 +243,7 @@ hipError_t launch_one(const SweepLaunch &L) {
     // One strip per resident wavefront slot, each as tall as that allows
     // (a second round of strips measured slower than taller strips, whose
     // 2KR redundant rows cost less); at least 4KR rows.
-    static const int slots = resident_blocks(k_sweep2d_tb<R, MASK, K, false>);
+    static const int slots = resident_blocks(k_sweep2d_tb<T, R, MASK, K, false>);
     const int tiles_y = std::max(1, slots / tiles_x);
     by = std::max((ny + tiles_y - 1) / tiles_y, 4 * K * R);
   }
@@ -239,64 +253,38 @@ hipError_t launch_one(const SweepLaunch &L) {
   if (blocks > (1LL << 31) - 1) return hipErrorNotSupported;
   const int4 zbox = {L.zbox[0], L.zbox[1], L.zbox[2], L.zbox[3]};
   if (L.zb)
-    hipLaunchKernelGGL((k_sweep2d_tb<R, MASK, K, true>), dim3((unsigned)blocks), dim3(64), 0,
-                       L.stream, (const float *)L.in, (float *)L.out, ny, nx, by, tiles_x, W, zbox,
-                       (float)L.zval);
+    hipLaunchKernelGGL((k_sweep2d_tb<T, R, MASK, K, true>), dim3((unsigned)blocks), dim3(64), 0,
+                       L.stream, (const T *)L.in, (T *)L.out, ny, nx, by, tiles_x, W, zbox,
+                       (T)L.zval);
   else
-    hipLaunchKernelGGL((k_sweep2d_tb<R, MASK, K, false>), dim3((unsigned)blocks), dim3(64), 0,
-                       L.stream, (const float *)L.in, (float *)L.out, ny, nx, by, tiles_x, W, zbox,
-                       0.0f);
+    hipLaunchKernelGGL((k_sweep2d_tb<T, R, MASK, K, false>), dim3((unsigned)blocks), dim3(64), 0,
+                       L.stream, (const T *)L.in, (T *)L.out, ny, nx, by, tiles_x, W, zbox, T(0));
   return hipGetLastError();
 }
 
-template <int R, int MASK>
-hipError_t launch_k(const SweepLaunch &L);
+// The launch of L.steps (2 .. KMAX) fused applications.
+template <typename T, int R, int MASK, int... Ks>
+hipError_t launch_ks(const SweepLaunch &L, std::integer_sequence<int, Ks...>) {
+  hipError_t e = hipErrorNotSupported;
+  ((L.steps == Ks + 2 ? (void)(e = launch_one<T, R, MASK, Ks + 2>(L)) : (void)0), ...);
+  return e;
+}
+template <typename T, int R, int MASK, int KMAX>
+hipError_t launch_upto(const SweepLaunch &L) {
+  return launch_ks<T, R, MASK>(L, std::make_integer_sequence<int, KMAX - 1>{});
+}
 
-#define TB_CASE(R, MASK, K) \
-  case K: return launch_one<R, MASK, K>(L);
-
-template <>
-hipError_t launch_k<1, MASK_BOX>(const SweepLaunch &L) {
-  switch (L.steps) { TB_CASE(1, MASK_BOX, 2) TB_CASE(1, MASK_BOX, 3) TB_CASE(1, MASK_BOX, 4)
-    TB_CASE(1, MASK_BOX, 5) TB_CASE(1, MASK_BOX, 6) TB_CASE(1, MASK_BOX, 7) TB_CASE(1, MASK_BOX, 8) }
-  return hipErrorNotSupported;
-}
-template <>
-hipError_t launch_k<1, MASK_DIAMOND>(const SweepLaunch &L) {
-  switch (L.steps) { TB_CASE(1, MASK_DIAMOND, 2) TB_CASE(1, MASK_DIAMOND, 3) TB_CASE(1, MASK_DIAMOND, 4)
-    TB_CASE(1, MASK_DIAMOND, 5) TB_CASE(1, MASK_DIAMOND, 6) TB_CASE(1, MASK_DIAMOND, 7)
-    TB_CASE(1, MASK_DIAMOND, 8) TB_CASE(1, MASK_DIAMOND, 9) TB_CASE(1, MASK_DIAMOND, 10)
-    TB_CASE(1, MASK_DIAMOND, 11) TB_CASE(1, MASK_DIAMOND, 12) }
-  return hipErrorNotSupported;
-}
-template <>
-hipError_t launch_k<2, MASK_BOX>(const SweepLaunch &L) {
-  switch (L.steps) { TB_CASE(2, MASK_BOX, 2) TB_CASE(2, MASK_BOX, 3) TB_CASE(2, MASK_BOX, 4) }
-  return hipErrorNotSupported;
-}
-template <>
-hipError_t launch_k<2, MASK_DIAMOND>(const SweepLaunch &L) {
-  switch (L.steps) { TB_CASE(2, MASK_DIAMOND, 2) TB_CASE(2, MASK_DIAMOND, 3) TB_CASE(2, MASK_DIAMOND, 4) }
-  return hipErrorNotSupported;
-}
-template <>
-hipError_t launch_k<3, MASK_DIAMOND>(const SweepLaunch &L) {
-  switch (L.steps) { TB_CASE(3, MASK_DIAMOND, 2) }
-  return hipErrorNotSupported;
-}
-template <>
-hipError_t launch_k<4, MASK_DIAMOND>(const SweepLaunch &L) {
-  switch (L.steps) { TB_CASE(4, MASK_DIAMOND, 2) }
-  return hipErrorNotSupported;
-}
-#undef TB_CASE
-
-// Most steps per pass by radius: the queue (K*(2R+1)*4 registers) and two
-// groups of 2R+1 prefetched rows must leave room for two or more waves/SIMD.
-// Boxes of radius 3 and more (49+ taps per point) are bound by FMA issue in
-// one step per pass already, and fusing only adds the redundant border work.
-int tb_max(int R, int mask) {
+// Most steps per pass by radius: the queue (K*(2R+1)*4 values per lane) and
+// two groups of 2R+1 prefetched rows must leave room for two or more
+// waves/SIMD (FP64 values take two registers).  Boxes of radius 3 and more
+// (49+ taps per point) are bound by FMA issue in one step per pass already,
+// and fusing only adds the redundant border work.
+int tb_max(int R, int mask, int dtype) {
   if (mask == MASK_BOX && R >= 3) return 1;
+  if (dtype == STENCIL_F64) {
+    if (R == 1) return mask == MASK_BOX ? 4 : 6;
+    return R == 2 ? 2 : 1;
+  }
   static const int star1 = [] {
     const char *e = std::getenv("STENCIL_TB_STAR_K");
     return e ? std::max(2, std::min(12, std::atoi(e))) : 12;
@@ -305,12 +293,32 @@ int tb_max(int R, int mask) {
   return R == 1 ? 8 : R == 2 ? 4 : R <= 4 ? 2 : 1;
 }
 
+template <typename T>
+hipError_t launch_t(const SweepLaunch &L) {
+  const bool box = L.op->mask == MASK_BOX;  // the diamond contains the axes
+  if constexpr (sizeof(T) == 4) {
+    switch (L.op->R) {
+      case 1: return box ? launch_upto<T, 1, MASK_BOX, 8>(L) : launch_upto<T, 1, MASK_DIAMOND, 12>(L);
+      case 2: return box ? launch_upto<T, 2, MASK_BOX, 4>(L) : launch_upto<T, 2, MASK_DIAMOND, 4>(L);
+      case 3: return box ? hipErrorNotSupported : launch_upto<T, 3, MASK_DIAMOND, 2>(L);
+      case 4: return box ? hipErrorNotSupported : launch_upto<T, 4, MASK_DIAMOND, 2>(L);
+      default: return hipErrorNotSupported;
+    }
+  } else {
+    switch (L.op->R) {
+      case 1: return box ? launch_upto<T, 1, MASK_BOX, 4>(L) : launch_upto<T, 1, MASK_DIAMOND, 6>(L);
+      case 2: return box ? launch_upto<T, 2, MASK_BOX, 2>(L) : launch_upto<T, 2, MASK_DIAMOND, 2>(L);
+      default: return hipErrorNotSupported;
+    }
+  }
+}
+
 }  // namespace
 
 int sweep2d_max_steps(const SweepLaunch &L) {
   const int R = L.op->R;
-  const int K = tb_max(R, L.op->mask);
-  if (K < 2 || L.dtype != STENCIL_F32 || L.g.dim != 2) return 1;
+  const int K = tb_max(R, L.op->mask, L.dtype);
+  if (K < 2 || L.g.dim != 2) return 1;
   if (L.g.nx % kVX != 0 || L.g.nx < kSpan || L.g.ny < 2 * K * R + 1) return 1;
   if (L.g.nx > (1 << 30) || L.g.ny > (1 << 30)) return 1;
   return K;
@@ -319,14 +327,7 @@ int sweep2d_max_steps(const SweepLaunch &L) {
 hipError_t launch_sweep2d_tb(const SweepLaunch &L) {
   if (L.steps < 2 || L.steps > sweep2d_max_steps(L)) return hipErrorNotSupported;
   if ((uintptr_t)L.in % 16 != 0 || (uintptr_t)L.out % 16 != 0) return hipErrorNotSupported;
-  const bool box = L.op->mask == MASK_BOX;  // the diamond contains the axes
-  switch (L.op->R) {
-    case 1: return box ? launch_k<1, MASK_BOX>(L) : launch_k<1, MASK_DIAMOND>(L);
-    case 2: return box ? launch_k<2, MASK_BOX>(L) : launch_k<2, MASK_DIAMOND>(L);
-    case 3: return box ? hipErrorNotSupported : launch_k<3, MASK_DIAMOND>(L);
-    case 4: return box ? hipErrorNotSupported : launch_k<4, MASK_DIAMOND>(L);
-    default: return hipErrorNotSupported;
-  }
+  return L.dtype == STENCIL_F32 ? launch_t<float>(L) : launch_t<double>(L);
 }
 
 }  // namespace stencil

@@ -151,6 +151,10 @@ def _make_workloads(seed: int = SEED) -> dict:
         to_f32_exact(star2d_weights(0.6, 0.1)), (1, 2, 4),
         "2D 5-point star (0.6; 0.1 x4), 8192^2 FP32, T=1000, zero Dirichlet boundaries; "
         "plain, fold m=2, m=4", {"boundary": "zero"})
+    # the 2D star in FP64 (the paper's precision), plain and folded
+    wl["star2d_f64"] = Workload(
+        "star2d_f64", 2, (8192, 8192), "f64", 1000, STAR, star2d_weights(0.6, 0.1), (1, 2),
+        "2D 5-point star (0.6; 0.1 x4), 8192^2 FP64, T=1000; plain, fold m=2")
     # the paper's worked example (Section 3.3): the unit 9-point box, here
     # normalised (each weight fl32(1/9)), whose folds are rank one
     wl["unitbox2d"] = Workload(
