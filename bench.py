@@ -22,8 +22,8 @@ weights prepared beforehand and the grid resident in HBM.
 The line's top-level fields describe star2d's fastest form; "configs" holds
 the same fields for every workload.  --workload X runs one workload alone
 (profiling runs), and also the extras: Table 1's box1d5p, apop1d and
-life2d, the unit box unitbox2d, the zero-boundary star2d_dirichlet and the
-FP64 star star2d_f64.
+life2d, the unit boxes unitbox2d and unitbox3d, the zero-boundary
+star2d_dirichlet and the FP64 star star2d_f64.
 
 Prints ONE JSON line on stdout.
 """
@@ -73,8 +73,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="all",
                     choices=["all", "star2d", "heat1d", "star3d", "box3d", "box2d", "unitbox2d",
-                             "star2d_dirichlet", "star2d_f64", "box1d5p", "apop1d", "life2d",
-                             "batched"])
+                             "star2d_dirichlet", "star2d_f64", "unitbox3d", "box1d5p", "apop1d",
+                             "life2d", "batched"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the FP64 oracle reference (profiling runs)")
@@ -118,6 +118,7 @@ KERNEL_SOURCES = {
     "sweep2dtb": ("sweep2d_tb.hip", "sweep2d_common.h"),
     "sweep3d": ("sweep3d.hip",),
     "sweep3dtb": ("sweep3d_tb.hip",),
+    "sweep3dsep": ("sweep3d_sep.hip",),
     "mfma2d": ("mfma2d.hip",),
     "batched": ("batched.hip", "sweep2d_common.h", "sweep2d_impl.h"),
 }
@@ -328,9 +329,10 @@ def bench_grid(args, wl_name, default_run=False):
                 form_modes.append(("vector_unfused", sf.STENCIL_MODE_VECTOR, 1))
         if symmetric:
             form_modes.append(("symmetric", sf.STENCIL_MODE_SYMMETRIC, 0))
-        if wl.dim == 2 and f32 and m > 1:
+        if (wl.dim == 2 and f32 and m > 1) or (wl.dim == 3 and f32):
             probe = sf.Plan(w, wl.shape_kind)
-            probe.fold(m)
+            if m > 1:
+                probe.fold(m)
             if probe.separable()[1]:
                 form_modes.append(("separable", sf.STENCIL_MODE_SEPARABLE, 0))
             probe.close()
@@ -387,7 +389,7 @@ def bench_grid(args, wl_name, default_run=False):
             # pass per rank-one term)
             fmas = taps
             if mode_name == "separable":
-                fmas = 2 * plan.separable()[0] * (2 * m * r + 1)
+                fmas = (2 * plan.separable()[0] if wl.dim == 2 else 3) * (2 * m * r + 1)
             flops = 2 * fmas * n * per_launch
             key = "%s_m%d_%s" % (wl_name, m, mode_name)
             gate = (1e-3 if mode_name == "mfma_bf16x3" else 1e-5) if f32 else 1e-12
@@ -452,15 +454,19 @@ def bench_grid(args, wl_name, default_run=False):
             "vector_graph": ("sweep%dd%s_m%d" % (wl.dim, "tb" if fused else "", m)),
             "vector_unfused": "sweep%dd_m%d" % (wl.dim, m),
             "symmetric": "sweep%dd_m%d_symmetric" % (wl.dim, m),
-            "separable": "sweep%dd_m%d_separable" % (wl.dim, m),
+            "separable": ("sweep%dd_m%d_separable" % (wl.dim, m) if wl.dim == 2
+                          else "sweep3dsep_m%d" % m),
             "mfma_bf16x3": "mfma2d_m%d" % m}[mode_name]
     roof["traffic"] = traffic_from_profiles(tkey, wl_name)
+    kname = ("k_sweep%dd_tb" % wl.dim) if fused else ("k_mfma2d" if mode_name.startswith("mfma")
+                                                      else "k_sweep%dd" % wl.dim)
+    if mode_name == "separable" and wl.dim == 3:
+        kname = "k_sweep3d_sep"
     roof["kernel"] = "%s R=%d (%s, %d taps, %.2f applications per launch)" % (
-        ("k_sweep%dd_tb" % wl.dim) if fused else ("k_mfma2d" if mode_name.startswith("mfma")
-                                                  else "k_sweep%dd" % wl.dim),
+        kname,
         m * r, mode_name, taps, per_launch)
-    roof["flops_basis"] = ("2 x FMAs per point (dense taps; 2 x rank x (2R+1) for the separable "
-                           "form) x points x applications per launch")
+    roof["flops_basis"] = ("2 x FMAs per point (dense taps; 2 x rank x (2R+1) for the 2D separable "
+                           "form, 3 x (2R+1) for the 3D one) x points x applications per launch")
     # speedups of the folded / matrix-core forms over the plain sweep
     plain_fused = forms.get("%s_m1_vector" % wl_name, {}).get("gstencil_s")
     plain_unfused = (forms.get("%s_m1_vector_unfused" % wl_name, {}).get("gstencil_s")

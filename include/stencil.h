@@ -54,6 +54,7 @@ enum {
                                    separable terms: a horizontal then a
                                    vertical 1D pass per term (the vertical and
                                    horizontal folding of Section 3.3, Eq. 4-6);
+                                   3D products a (x) b (x) c as three passes;
                                    other operators run as VECTOR             */
 };
 enum {
@@ -141,10 +142,12 @@ int stencil_fold_weights_f32(stencil_plan p, float *out, int64_t *out_len);
  * SYMMETRIC requires a 2D plan; it applies to operators with
  * w[dy][dx] == w[dy][-dx] == w[-dy][dx] on grids whose rows are whole
  * 16-byte vectors, and otherwise runs the VECTOR kernels.  SEPARABLE requires
- * a 2D plan; it applies to FP32 grids whose rows are whole 16-byte vectors
- * when stencil_plan_separable reports that it applies (radius m*r from 2 to
- * 8), with factors rounded to FP32 keeping each factor's sum, and otherwise
- * runs the VECTOR kernels.  VECTOR and EXACT_ORDER keep the canonical
+ * a 2D or 3D plan; in 2D it applies to FP32 grids whose rows are whole
+ * 16-byte vectors when stencil_plan_separable reports that it applies
+ * (radius m*r from 2 to 8), in 3D to FP32 grids when the operator is a
+ * product a (x) b (x) c (radius m*r up to 4: an x-pass, a y-pass and a
+ * z-pass, 3(2mr+1) FMAs per point), with factors rounded to FP32 keeping
+ * each factor's sum, and otherwise runs the VECTOR kernels.  VECTOR and EXACT_ORDER keep the canonical
  * summation order (acc = +0, one FMA per tap, row-major offsets);
  * MFMA_BF16X3, SYMMETRIC and SEPARABLE do not.
  * Errors: E_ARG, E_UNSUPPORTED.
@@ -200,8 +203,11 @@ int stencil_plan_set_graph(stencil_plan p, int on);
  * it), and whether STENCIL_MODE_SEPARABLE applies it: rank 1 or 2 and
  * 2 * rank * (2mr+1) FMAs per point fewer than its nonzero taps.  The
  * paper's unit box folds to rank 1 for every m (Section 3.3, Eq. 4); the
- * 5-point star folds to rank m+1.  rank and applies are nullable; a plan of
- * another dimension reports 0 and 0.  Errors: E_ARG.  No device work.
+ * 5-point star folds to rank m+1.  3D plans: rank 1 if the operator is a
+ * product a (x) b (x) c (every weight matches to 1e-12 of the largest), else
+ * 0; applies if so and 3 * (2mr+1) is fewer than the nonzero taps.  rank
+ * and applies are nullable; a 1D plan reports 0 and 0.  Errors: E_ARG.  No
+ * device work.
  */
 int stencil_plan_separable(stencil_plan p, int *rank, int *applies);
 

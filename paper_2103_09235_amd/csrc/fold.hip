@@ -181,6 +181,38 @@ int low_rank_2d(const std::vector<double> &W, int S, int max_rank, std::vector<d
   return rank;
 }
 
+// W (S x S x S, row-major [dz][dy][dx]) = a (x) b (x) c: the line of W
+// through its largest entry along each axis gives the factor up to scale
+// (for a product, W[:, y*, x*] / p, W[z*, :, x*] / p and W[z*, y*, :] / p
+// with p = W[z*, y*, x*] are the normalised factors and W = p a b c); the
+// scale is split evenly (cube root of p) so the three factors have equal
+// size.  Returns false unless every entry matches to 1e-12 of the largest.
+bool product_3d(const std::vector<double> &W, int S, std::vector<double> &a,
+                std::vector<double> &b, std::vector<double> &c) {
+  if ((int)W.size() != S * S * S) return false;
+  int best = 0;
+  for (int i = 1; i < S * S * S; ++i)
+    if (std::fabs(W[i]) > std::fabs(W[best])) best = i;
+  const double p = W[best];
+  if (p == 0.0) return false;
+  const int zs = best / (S * S), ys = (best / S) % S, xs = best % S;
+  const double g = std::cbrt(p);
+  a.assign(S, 0.0);
+  b.assign(S, 0.0);
+  c.assign(S, 0.0);
+  for (int i = 0; i < S; ++i) {
+    a[i] = W[(i * S + ys) * S + xs] / p * g;
+    b[i] = W[(zs * S + i) * S + xs] / p * g;
+    c[i] = W[(zs * S + ys) * S + i] / p * g;
+  }
+  const double tol = 1e-12 * std::fabs(p);
+  for (int z = 0; z < S; ++z)
+    for (int y = 0; y < S; ++y)
+      for (int x = 0; x < S; ++x)
+        if (std::fabs(W[(z * S + y) * S + x] - a[z] * b[y] * c[x]) > tol) return false;
+  return true;
+}
+
 // FP32 factors with each vector's total kept: entries rounded to nearest,
 // then the centre entry set to fl32(sum64 - sum of the other rounded
 // entries), so the FP32 operator's total weight sum_j (sum a_j)(sum b_j)

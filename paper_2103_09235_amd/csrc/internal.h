@@ -52,9 +52,10 @@ struct OperatorDev {
   std::vector<double> w64;
   void *mfma_b = nullptr;    // BF16 hi/lo B-fragment table (2D FP32, R <= 8)
   bool symmetric = false;    // 2D: w[dy][dx] == w[dy][-dx] == w[-dy][dx]
-  int sep_rank = 0;          // 2D FP32: rank 1 or 2 of a separable form that is
-                             // cheaper than the dense taps, else 0
-  std::vector<float> sep32;  // its factors a_0.., then b_0.. (2R+1 each)
+  int sep_rank = 0;          // FP32: rank 1 or 2 (2D) or 1 (3D products) of a
+                             // separable form cheaper than the dense taps, else 0
+  std::vector<float> sep32;  // its factors: 2D a_0.., then b_0..; 3D a (z), b (y),
+                             // c (x); 2R+1 each
 };
 
 // Per-device state owned by a plan.
@@ -113,6 +114,9 @@ uint16_t bf16_rne(float x);
 // elimination; returns the rank (max_rank + 1 if it is larger).
 int low_rank_2d(const std::vector<double> &W, int S, int max_rank, std::vector<double> &a,
                 std::vector<double> &b);
+// W (S x S x S) = a (x) b (x) c to 1e-12 of its largest entry: the factors.
+bool product_3d(const std::vector<double> &W, int S, std::vector<double> &a,
+                std::vector<double> &b, std::vector<double> &c);
 // FP32 rounding of factor vectors (S each) keeping each vector's sum.
 void round_factors_f32(const std::vector<double> &f, int S, std::vector<float> &out);
 void profitability(const std::vector<double> &w, int dim, int r, int m,
@@ -163,6 +167,9 @@ int sweep1d_max_steps(const SweepLaunch &L);
 // the launch of 2 <= L.steps <= that many steps.
 int sweep2d_max_steps(const SweepLaunch &L);
 hipError_t launch_sweep2d_tb(const SweepLaunch &L);
+// 3D FP32 operators of tensor rank one (op.sep_rank == 1, op.sep32 = the
+// z, y and x factors): three 1D passes per point.
+hipError_t launch_sweep3d_sep(const SweepLaunch &L);
 // 3D FP32 temporal blocking: the most applications one launch fuses (1 =
 // none), and the launch of 2 <= L.steps <= that many.
 int sweep3d_max_steps(const SweepLaunch &L);

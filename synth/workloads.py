@@ -162,6 +162,13 @@ def _make_workloads(seed: int = SEED) -> dict:
         to_f32_exact(np.full((3, 3), 1.0 / 9.0)), (1, 4, 8),
         "2D unit 9-point box (each weight 1/9), 16384^2 FP32, T=400; plain, fold m=4 "
         "and m=8, dense, separable (rank one) and BF16x3 MFMA")
+    # the unit box in 3D (each weight fl32(1/27)): a product of three 1D
+    # weights, folded or not
+    wl["unitbox3d"] = Workload(
+        "unitbox3d", 3, (512, 512, 512), "f32", 200, BOX,
+        to_f32_exact(np.full((3, 3, 3), 1.0 / 27.0)), (1, 2),
+        "3D unit 27-point box (each weight 1/27), 512^3 FP32, T=200; plain and fold m=2, "
+        "dense and separable (a product of three 1D weights)")
     return wl
 
 

@@ -299,11 +299,20 @@ def test_separable_rank_and_mode():
     d = np.array([0.0, 1, 0, 1, 0])
     w3 = (np.outer(a, b) + np.outer(c, a) + np.outer(d, c)) / 300
     assert sf.Plan(w3, sf.STENCIL_BOX).separable() == (3, False)
-    assert sf.Plan(np.ones((3, 3, 3)), sf.STENCIL_BOX).separable() == (0, False)
     unit.set_mode(sf.STENCIL_MODE_SEPARABLE)
     assert unit.info()["mode"] == sf.STENCIL_MODE_SEPARABLE
+    # 3D: products a (x) b (x) c (9 FMAs < 27 taps), not the random box or the star
+    assert sf.Plan(np.ones((3, 3, 3)), sf.STENCIL_BOX).separable() == (1, True)
+    p3 = np.einsum("i,j,k->ijk", a[1:4], c[1:4], b[1:4] + 1.0)
+    assert sf.Plan(p3 / p3.sum(), sf.STENCIL_BOX).separable() == (1, True)
+    assert sf.Plan(synth.random_positive_weights(3, 1), sf.STENCIL_BOX).separable() == (0, False)
+    assert sf.Plan(synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR).separable() == (0, False)
+    q3 = p3.copy()
+    q3[0, 0, 0] *= 1.0 + 1e-9  # no longer a product
+    assert sf.Plan(q3, sf.STENCIL_BOX).separable() == (0, False)
+    sf.Plan(np.ones((3, 3, 3)), sf.STENCIL_BOX).set_mode(sf.STENCIL_MODE_SEPARABLE)
     with pytest.raises(sf.StencilError) as e:
-        sf.Plan(np.ones((3, 3, 3)), sf.STENCIL_BOX).set_mode(sf.STENCIL_MODE_SEPARABLE)
+        sf.Plan(synth.heat1d_weights(), sf.STENCIL_STAR).set_mode(sf.STENCIL_MODE_SEPARABLE)
     assert e.value.code == sf.STENCIL_E_UNSUPPORTED
     # SEPARABLE runs one application per launch
     s = sf.stencil_run_schedule(unit.handle, (1024, 1024), sf.STENCIL_F32, 16, 1 << 20)
