@@ -201,12 +201,18 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
     for (int k = 0; k < NU; ++k)
 #pragma unroll
       for (int v = 0; v < VX; ++v) acc[st][k][v] = 0.0f;
-  auto row = [&](const int j, const int u, const float (&in_row)[VX]) {
+  // One level-0 row j through the stages; u = (j - jstart) mod NU.  NA: the
+  // number of stages (a compile-time count), or -1: stage st from
+  // j - jstart = 2 st R on.
+  auto row = [&](const int j, const int u, const float (&in_row)[VX], auto na)
+                 __attribute__((always_inline)) {
+    constexpr int NA = decltype(na)::value;
     float cur[VX];
 #pragma unroll
     for (int v = 0; v < VX; ++v) cur[v] = in_row[v];
 #pragma unroll
-    for (int st = 0; st < K; ++st) {
+    for (int st = 0; st < (NA < 0 ? K : NA); ++st) {
+      if (NA < 0 && j - jstart < 2 * st * R) break;  // uniform: later stages start later
       {
         float win[VX + 2 * R];
 #pragma unroll
@@ -247,7 +253,7 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
       }
     }
   };
-  auto fetch = [&](const int j0, float (&buf)[NU][VX]) {
+  auto fetch = [&](const int j0, float (&buf)[NU][VX]) __attribute__((always_inline)) {
 #pragma unroll
     for (int p = 0; p < NU; ++p) {
       const float *rowp = in + (size_t)wrap1(min(j0 + p, jend - 1), ny) * nx;
@@ -261,14 +267,25 @@ __device__ void tb_strip(const float *__restrict__ in, float *__restrict__ out, 
   };
   float bufA[NU][VX], bufB[NU][VX];
   fetch(jstart, bufA);
-  for (int jb = jstart; jb < jend; jb += 2 * NU) {
+  // Stage st computes nothing that a stored row depends on before streamed
+  // row 2 st R (as in the single-grid fused kernel): the first PG groups of
+  // NU rows run only the stages that matter (R*K*(K-1) of a strip's
+  // K*(BY + 2KR) stage-rows skipped).  Rows past jend are skipped too (a
+  // uniform branch per row; their loads stay unconditional).
+  constexpr int PG = ((2 * (K - 1) * R + NU - 1) / NU + 1) / 2 * 2;
+  auto pair = [&](const int jb, auto na) __attribute__((always_inline)) {
     fetch(jb + NU, bufB);
 #pragma unroll
-    for (int u = 0; u < NU; ++u) row(jb + u, u, bufA[u]);
+    for (int u = 0; u < NU; ++u)
+      if (jb + u < jend) row(jb + u, u, bufA[u], na);
     fetch(jb + 2 * NU, bufA);
 #pragma unroll
-    for (int u = 0; u < NU; ++u) row(jb + NU + u, u, bufB[u]);
-  }
+    for (int u = 0; u < NU; ++u)
+      if (jb + NU + u < jend) row(jb + NU + u, u, bufB[u], na);
+  };
+  int jb = jstart;
+  for (; jb < jstart + PG * NU; jb += 2 * NU) pair(jb, std::integral_constant<int, -1>{});
+  for (; jb < jend; jb += 2 * NU) pair(jb, std::integral_constant<int, K>{});
 }
 
 // Pass k of every fused grid whose pass k has KC applications: one block per

@@ -80,6 +80,15 @@ __device__ __forceinline__ double lane_from_right(double x) {
       __builtin_amdgcn_update_dpp(0, h.y, 0x130, 0xF, 0xF, true)));
 }
 
+template <typename F, int... Ks>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Ks...>) {
+  (f(std::integral_constant<int, Ks>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // One strip (tile t).  ZB: zero every stage's output outside zbox.
 template <typename T, int R, int MASK, int K, bool ZB>
 __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict__ out,
@@ -122,15 +131,22 @@ __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict_
 #pragma unroll
       for (int v = 0; v < kVX; ++v) acc[s][k][v] = T(0);
 
-  // One level-0 row j through the K stages; u = (j - jstart) mod NU.
-  auto row = [&](const int j, const int u, const T (&in_row)[kVX]) {
+  // One level-0 row j through the K stages; u = (j - jstart) mod NU.  PRO
+  // (the first rows of a strip): stage s runs only from j - jstart = 2sR on.
+  auto row = [&](const int j, const int u, const T (&in_row)[kVX], auto na)
+                 __attribute__((always_inline)) {
+    // NA: stages to run (a compile-time count), or -1: stage s from
+    // j - jstart = 2sR on
+    constexpr int NA = decltype(na)::value;
+    constexpr bool PRO = NA < 0;
     T cur[kVX];
 #pragma unroll
     for (int v = 0; v < kVX; ++v) cur[v] = in_row[v];
     // Stage s takes level-s row j - s*R and finishes level-(s+1) row
     // j - (s+1)*R; the slot of an output row is fixed by its index mod NU.
 #pragma unroll
-    for (int s = 0; s < K; ++s) {
+    for (int s = 0; s < (NA < 0 ? K : NA); ++s) {
+      if (PRO && j - jstart < 2 * s * R) break;  // uniform: later stages start later
       // the R columns on either side come from the neighbouring lanes
       T win[kVX + 2 * R];
 #pragma unroll
@@ -169,7 +185,7 @@ __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict_
         }
       }
     }
-    const int yd = j - K * R;  // level-K row just completed
+    const int yd = j - K * R;  // level-K row just completed (all stages ran)
     if (store_ok && yd >= y0 && yd < y1) store_vec<T, kVX>(out + (size_t)yd * nx + xo0 + lo, cur);
   };
 
@@ -179,23 +195,56 @@ __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict_
   // alternate, so no register with a load in flight is ever copied (a copy
   // makes the compiler wait for every outstanding access), and the loads are
   // unconditional for the same reason: rows past the end re-read the last.
-  auto fetch = [&](const int j0, T (&buf)[NU][kVX]) {
+  auto fetch = [&](const int j0, T (&buf)[NU][kVX]) __attribute__((always_inline)) {
 #pragma unroll
     for (int p = 0; p < NU; ++p)
       load_vec<T, kVX>(in + (size_t)wrap1(min(j0 + p, jend - 1), ny) * nx + gx, buf[p]);
   };
   T bufA[NU][kVX], bufB[NU][kVX];
   fetch(jstart, bufA);
+  // The first level-s row that a stored row depends on is streamed at index
+  // 2sR (index = j - jstart): before it stage s computes nothing that is
+  // kept (its earlier outputs lie outside the strip's dependency trapezoid
+  // and reach stage s+1 only before that stage starts).  The first PG groups
+  // of NU rows run only the stages that matter, which skips R*K*(K-1) of the
+  // strip's K*(BY + 2KR) stage-rows.  Every output slot restarts from +0 at
+  // its first tap, so a stage that starts late needs no cleared queue.
+  constexpr int PG = ((2 * (K - 1) * R + NU - 1) / NU + 1) / 2 * 2;
+  // (unrolled for FP32 operators of radius <= 2; for the others the unrolled
+  // form raised the registers past an occupancy step or measured slower)
+  constexpr bool kStaticPrologue = sizeof(T) == 4 && R <= 2;
   // Pairs of NU-row groups: up to 2NU-1 rows past jend are computed and
-  // dropped.
-  for (int jb = jstart; jb < jend; jb += 2 * NU) {
+  // dropped (the launch sizes strips to avoid them).
+  auto pair = [&](const int jb, auto pro) __attribute__((always_inline)) {
     fetch(jb + NU, bufB);
 #pragma unroll
-    for (int u = 0; u < NU; ++u) row(jb + u, u, bufA[u]);
+    for (int u = 0; u < NU; ++u) row(jb + u, u, bufA[u], pro);
     fetch(jb + 2 * NU, bufA);
 #pragma unroll
-    for (int u = 0; u < NU; ++u) row(jb + NU + u, u, bufB[u]);
+    for (int u = 0; u < NU; ++u) row(jb + NU + u, u, bufB[u], pro);
+  };
+  int jb = jstart;
+  if constexpr (kStaticPrologue) {
+    // unrolled: row i of the prologue runs its min(K, i/(2R) + 1) stages
+    static_for<PG / 2>([&](auto pc) __attribute__((always_inline)) {
+      constexpr int p0 = 2 * decltype(pc)::value * NU;
+      fetch(jb + p0 + NU, bufB);
+      static_for<NU>([&](auto uc) __attribute__((always_inline)) {
+        constexpr int u = decltype(uc)::value;
+        row(jb + p0 + u, u, bufA[u], std::integral_constant<int, std::min(K, (p0 + u) / (2 * R) + 1)>{});
+      });
+      fetch(jb + p0 + 2 * NU, bufA);
+      static_for<NU>([&](auto uc) __attribute__((always_inline)) {
+        constexpr int u = decltype(uc)::value;
+        row(jb + p0 + NU + u, u, bufB[u],
+            std::integral_constant<int, std::min(K, (p0 + NU + u) / (2 * R) + 1)>{});
+      });
+    });
+    jb += PG * NU;
+  } else {
+    for (; jb < jstart + PG * NU; jb += 2 * NU) pair(jb, std::integral_constant<int, -1>{});
   }
+  for (; jb < jend; jb += 2 * NU) pair(jb, std::integral_constant<int, K>{});
 }
 
 // All strips of a launch are resident at once (one per wavefront slot), so
@@ -246,6 +295,9 @@ hipError_t launch_one(const SweepLaunch &L) {
     static const int slots = resident_blocks(k_sweep2d_tb<T, R, MASK, K, false>);
     const int tiles_y = std::max(1, slots / tiles_x);
     by = std::max((ny + tiles_y - 1) / tiles_y, 4 * K * R);
+    // whole pairs of (2R+1)-row groups per strip: no rows past its end
+    const int pair = 2 * S;
+    by += (pair - (by + 2 * K * R) % pair) % pair;
   }
   by = std::min(by, ny);
   const int tiles_y = (ny + by - 1) / by;
