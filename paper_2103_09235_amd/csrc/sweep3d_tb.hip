@@ -140,12 +140,21 @@ k_sweep3d_tb(const float *__restrict__ in, float *__restrict__ out, int nz, int 
     for (int v = 0; v < NG; ++v)
       g0[i][v] = (size_t)gy * nx + wrapn(x0 - G::B(0) + 4 * cx + v, nx);
   }
+  // slots past the region re-read the thread's first run (always inside it)
+  static_assert(G::C(0) >= kThreads, "every thread owns a level-0 run");
+#pragma unroll
+  for (int i = 1; i < N0; ++i)
+#pragma unroll
+    for (int v = 0; v < NG; ++v)
+      if (off0[i] < 0) g0[i][v] = g0[0][v];
   float pf[2][N0][4];
+  // Every run slot is loaded (slots past the region re-read an in-grid
+  // point and are never stored): a load under a branch makes the compiler
+  // wait for every access in flight, which would drain the look-ahead.
   auto fetch = [&](int j, float(&buf)[N0][4]) __attribute__((always_inline)) {
     const float *plane = in + (size_t)wrapn(z0 - K * R + j, nz) * plane_sz;
 #pragma unroll
     for (int i = 0; i < N0; ++i) {
-      if (off0[i] < 0) continue;
       if constexpr (V == 4) {
         using V4 = __attribute__((ext_vector_type(4))) float;
         const V4 q = *reinterpret_cast<const V4 *>(plane + g0[i][0]);
