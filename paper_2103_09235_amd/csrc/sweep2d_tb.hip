@@ -3,16 +3,16 @@
 //
 // The paper keeps several steps of a tile on chip with tessellate tiling
 // (Section 3.4) so data is not reloaded between steps.  Here a wavefront
-// streams a 256-column strip down y through a pipeline of K stages: stage s
-// turns rows of time level s into rows of level s+1 with the accumulator
-// queue of the single-step kernel (2R+1 pending rows in registers, four
-// columns per lane, the R columns beyond them fetched from the neighbouring
-// lanes by DPP) and hands each finished row straight to stage s+1.  Only
-// level 0 is read from HBM and only level K is written.
+// streams a strip of 256 FP32 (128 FP64) columns down y through a pipeline of
+// K stages: stage s turns rows of time level s into rows of level s+1 with
+// the accumulator queue of the single-step kernel (2R+1 pending rows in
+// registers, 16 bytes of columns per lane, the R columns beyond them fetched
+// from the neighbouring lanes by DPP) and hands each finished row straight to
+// stage s+1.  Only level 0 is read from HBM and only level K is written.
 //
 // Each level loses R valid columns at both ends of the strip (strips do not
-// exchange halos), so a strip loads 256 columns and stores the middle
-// 256 - 2B, B = K*R rounded up to a whole 16-byte vector; rows likewise: a
+// exchange halos), so a strip loads its span of columns and stores the
+// middle span - 2B, B = K*R rounded up to a whole 16-byte vector; rows likewise: a
 // strip of BY output rows streams BY + 2KR input rows, and rows of a level
 // that lack history only ever feed rows of the next level that are not
 // stored.  Every stored value went through K plain steps in the canonical
@@ -43,10 +43,18 @@ using k2d::store_vec;
 using k2d::WArr;
 using k2d::wrap1;
 
-constexpr int kVX = 4;
-constexpr int kSpan = 64 * kVX;  // columns a wavefront holds
-
-__host__ __device__ constexpr int border(int K, int R) { return (K * R + kVX - 1) / kVX * kVX; }
+// A lane holds 16 bytes of a row (4 FP32 or 2 FP64 columns, one vector load
+// each, so a wavefront's load covers 1 KiB contiguously): a strip spans 256
+// FP32 or 128 FP64 columns.
+template <typename T>
+__host__ __device__ constexpr int lane_cols() { return 16 / (int)sizeof(T); }
+template <typename T>
+__host__ __device__ constexpr int span_cols() { return 64 * lane_cols<T>(); }
+// Columns a strip discards on each side: K*R rounded up to whole lanes.
+template <typename T>
+__host__ __device__ constexpr int border(int K, int R) {
+  return (K * R + lane_cols<T>() - 1) / lane_cols<T>() * lane_cols<T>();
+}
 
 // Blocks are dealt round-robin to the 8 XCDs (block b to XCD b mod 8):
 // renumber them so each XCD runs one contiguous range of strips, for any
@@ -97,7 +105,9 @@ __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict_
                                         int4 zbox, T zval, int t) {
   constexpr int S = 2 * R + 1;
   constexpr int NU = S;                        // queue length = unroll of the row loop
-  constexpr int B = border(K, R);
+  constexpr int kVX = lane_cols<T>();
+  constexpr int kSpan = span_cols<T>();
+  constexpr int B = border<T>(K, R);
   constexpr int WOUT = kSpan - 2 * B;          // stored columns per strip
   static_assert(WOUT > 0, "strip geometry");
   static_assert(R <= kVX, "halo columns come from the two neighbouring lanes");
@@ -108,9 +118,9 @@ __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict_
   const int xi0 = xo0 - B;       // first loaded column (a multiple of 4)
   const int y0 = ty * BY, y1 = min(y0 + BY, ny);
   const int jstart = y0 - K * R, jend = y1 + K * R;  // level-0 rows streamed
-  // The lane's four columns xi0 + 4*lane .. +3 wrap as a whole (nx % 4 == 0).
+  // The lane's columns xi0 + kVX*lane .. + kVX - 1 wrap as a whole (nx % kVX == 0).
   const int gx = wrap1(xi0 + kVX * lane, nx);
-  // Stored lanes: four columns inside [B, kSpan - B) and inside the grid.
+  // Stored lanes: their columns inside [B, kSpan - B) and inside the grid.
   const int lo = kVX * lane - B;
   const bool store_ok = lo >= 0 && lo + kVX <= WOUT && xo0 + lo + kVX <= nx;
   // ZB: the lane's columns inside the interior box (zbox = rows [x, y),
@@ -278,7 +288,7 @@ hipError_t launch_one(const SweepLaunch &L) {
                (int)L.g.nx - L.zbox[3] < R))
     return hipErrorInvalidValue;  // the pad must hold every read of the interior
   constexpr int S = 2 * R + 1;
-  constexpr int WOUT = kSpan - 2 * border(K, R);
+  constexpr int WOUT = span_cols<T>() - 2 * border<T>(K, R);
   WArr<T, S * S> W;
   for (int i = 0; i < S * S; ++i) W.v[i] = sizeof(T) == 4 ? (T)L.op->w32[i] : (T)L.op->w64[i];
   const int ny = (int)L.g.ny, nx = (int)L.g.nx;
@@ -326,22 +336,22 @@ hipError_t launch_upto(const SweepLaunch &L) {
   return launch_ks<T, R, MASK>(L, std::make_integer_sequence<int, KMAX - 1>{});
 }
 
-// Most steps per pass by radius: the queue (K*(2R+1)*4 values per lane) and
-// two groups of 2R+1 prefetched rows must leave room for two or more
-// waves/SIMD (FP64 values take two registers).  Boxes of radius 3 and more
+// Most steps per pass by radius: the queue (K*(2R+1) rows of 16 bytes per
+// lane) and two groups of 2R+1 prefetched rows must leave room for two or
+// more waves/SIMD.  Boxes of radius 3 and more
 // (49+ taps per point) are bound by FMA issue in one step per pass already,
 // and fusing only adds the redundant border work.
 int tb_max(int R, int mask, int dtype) {
   if (mask == MASK_BOX && R >= 3) return 1;
-  if (dtype == STENCIL_F64) {
-    if (R == 1) return mask == MASK_BOX ? 4 : 6;
-    return R == 2 ? 2 : 1;
-  }
   static const int star1 = [] {
     const char *e = std::getenv("STENCIL_TB_STAR_K");
-    return e ? std::max(2, std::min(12, std::atoi(e))) : 12;
+    return e ? std::max(2, std::min(12, std::atoi(e))) : 0;
   }();
-  if (R == 1 && mask != MASK_BOX) return star1;
+  if (dtype == STENCIL_F64) {
+    if (R == 1) return mask == MASK_BOX ? 8 : (star1 ? star1 : 12);
+    return R == 2 ? 4 : 1;
+  }
+  if (R == 1 && mask != MASK_BOX) return star1 ? star1 : 12;
   return R == 1 ? 8 : R == 2 ? 4 : R <= 4 ? 2 : 1;
 }
 
@@ -358,8 +368,8 @@ hipError_t launch_t(const SweepLaunch &L) {
     }
   } else {
     switch (L.op->R) {
-      case 1: return box ? launch_upto<T, 1, MASK_BOX, 4>(L) : launch_upto<T, 1, MASK_DIAMOND, 6>(L);
-      case 2: return box ? launch_upto<T, 2, MASK_BOX, 2>(L) : launch_upto<T, 2, MASK_DIAMOND, 2>(L);
+      case 1: return box ? launch_upto<T, 1, MASK_BOX, 8>(L) : launch_upto<T, 1, MASK_DIAMOND, 12>(L);
+      case 2: return box ? launch_upto<T, 2, MASK_BOX, 4>(L) : launch_upto<T, 2, MASK_DIAMOND, 4>(L);
       default: return hipErrorNotSupported;
     }
   }
@@ -371,7 +381,8 @@ int sweep2d_max_steps(const SweepLaunch &L) {
   const int R = L.op->R;
   const int K = tb_max(R, L.op->mask, L.dtype);
   if (K < 2 || L.g.dim != 2) return 1;
-  if (L.g.nx % kVX != 0 || L.g.nx < kSpan || L.g.ny < 2 * K * R + 1) return 1;
+  const int vx = L.dtype == STENCIL_F64 ? lane_cols<double>() : lane_cols<float>();
+  if (L.g.nx % vx != 0 || L.g.nx < 64 * vx || L.g.ny < 2 * K * R + 1) return 1;
   if (L.g.nx > (1 << 30) || L.g.ny > (1 << 30)) return 1;
   return K;
 }

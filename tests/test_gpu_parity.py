@@ -498,8 +498,11 @@ def test_separable_3d(case):
 
 TB64_CASES = [
     # (name, weights, kind, shape, T, m, fusion, boundary): FP64 2D grids
-    ("star_r1_k6", synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR, (150, 772), 13, 1, 0, "periodic"),
-    ("box_r1_k4", synth.random_positive_weights(2, 1), sf.STENCIL_BOX, (99, 516), 9, 1, 0,
+    ("star_r1_k12", synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR, (150, 772), 25, 1, 0,
+     "periodic"),
+    ("box_r1_k8", synth.random_positive_weights(2, 1), sf.STENCIL_BOX, (99, 516), 17, 1, 0,
+     "periodic"),
+    ("star_r1_ragged", synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR, (37, 130), 14, 1, 0,
      "periodic"),
     ("star_r1_k3", synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR, (40, 260), 7, 1, 3, "periodic"),
     ("star_m2_fused", synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR, (64, 512), 9, 2, 0,
