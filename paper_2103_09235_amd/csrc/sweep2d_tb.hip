@@ -97,12 +97,21 @@ __device__ __forceinline__ void static_for(F &&f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// One strip (tile t).  ZB: zero every stage's output outside zbox.
+// Strip layout of a launch: tiles_x strip columns; columns [mx0, mx1) hold
+// strips of by rows, the others (zero-boundary launches: the columns whose
+// strips hold pad columns, which mask every stage per lane) shorter strips
+// of by_m rows, numbered first.
+struct TbTiling {
+  int tiles_x, by, mx0, mx1, by_m, tiles_y_m;
+};
+
+// One strip (column tx, output rows [y0, y1)).  ZB: zero every stage's
+// output outside zbox.
 template <typename T, int R, int MASK, int K, bool ZB>
 __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict__ out,
-                                        int ny, int nx, int BY, int tiles_x,
+                                        int ny, int nx,
                                         const WArr<T, (2 * R + 1) * (2 * R + 1)> &W,
-                                        int4 zbox, T zval, int t) {
+                                        int4 zbox, T zval, int tx, int y0, int y1) {
   constexpr int S = 2 * R + 1;
   constexpr int NU = S;                        // queue length = unroll of the row loop
   constexpr int kVX = lane_cols<T>();
@@ -113,10 +122,8 @@ __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict_
   static_assert(R <= kVX, "halo columns come from the two neighbouring lanes");
 
   const int lane = threadIdx.x;
-  const int tx = t % tiles_x, ty = t / tiles_x;
   const int xo0 = tx * WOUT;     // first stored column of the strip
   const int xi0 = xo0 - B;       // first loaded column (a multiple of 4)
-  const int y0 = ty * BY, y1 = min(y0 + BY, ny);
   const int jstart = y0 - K * R, jend = y1 + K * R;  // level-0 rows streamed
   // The lane's columns xi0 + kVX*lane .. + kVX - 1 wrap as a whole (nx % kVX == 0).
   const int gx = wrap1(xi0 + kVX * lane, nx);
@@ -260,13 +267,28 @@ __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict_
 // All strips of a launch are resident at once (one per wavefront slot), so
 // the launch lasts as long as its slowest strip: a zero-boundary launch runs
 // the masked body in every strip (an unmasked body for the strips that hold
-// no pad cell measured no faster).
+// no pad cell measured no faster), and the strips that hold pad columns are
+// shorter.
 template <typename T, int R, int MASK, int K, bool ZB>
 __global__ void __launch_bounds__(64)
-k_sweep2d_tb(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, int BY,
-             int tiles_x, WArr<T, (2 * R + 1) * (2 * R + 1)> W, int4 zbox, T zval) {
-  tb_body<T, R, MASK, K, ZB>(in, out, ny, nx, BY, tiles_x, W, zbox, zval,
-                             xcd_contiguous(blockIdx.x, gridDim.x));
+k_sweep2d_tb(const T *__restrict__ in, T *__restrict__ out, int ny, int nx, TbTiling tl,
+             WArr<T, (2 * R + 1) * (2 * R + 1)> W, int4 zbox, T zval) {
+  int t = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int ncm = tl.mx0 + (tl.tiles_x - tl.mx1);  // strip columns of short strips
+  int tx, y0, by;
+  if (t < ncm * tl.tiles_y_m) {
+    const int c = t / tl.tiles_y_m;
+    tx = c < tl.mx0 ? c : tl.mx1 + (c - tl.mx0);
+    y0 = (t - c * tl.tiles_y_m) * tl.by_m;
+    by = tl.by_m;
+  } else {
+    t -= ncm * tl.tiles_y_m;
+    const int w = tl.mx1 - tl.mx0;
+    tx = tl.mx0 + t % w;
+    y0 = (t / w) * tl.by;
+    by = tl.by;
+  }
+  tb_body<T, R, MASK, K, ZB>(in, out, ny, nx, W, zbox, zval, tx, y0, min(y0 + by, ny));
 }
 
 // Wavefront slots the device holds at once for a kernel (one wave per block).
@@ -310,17 +332,39 @@ hipError_t launch_one(const SweepLaunch &L) {
     by += (pair - (by + 2 * K * R) % pair) % pair;
   }
   by = std::min(by, ny);
-  const int tiles_y = (ny + by - 1) / by;
-  const int64_t blocks = (int64_t)tiles_x * tiles_y;
+  TbTiling tl{tiles_x, by, 0, tiles_x, by, 1};
+  if (L.zb) {
+    // strip columns whose strips hold pad columns: a prefix and a suffix
+    constexpr int SPAN = span_cols<T>(), B = border<T>(K, R);
+    auto masked = [&](int tx) { return tx * WOUT - B < L.zbox[2] || tx * WOUT - B + SPAN > L.zbox[3]; };
+    int mx0 = 0, mx1 = tiles_x;
+    while (mx0 < tiles_x && masked(mx0)) ++mx0;
+    while (mx1 > mx0 && masked(mx1 - 1)) --mx1;
+    if (mx0 > 0 || mx1 < tiles_x) {
+      // their per-lane masking makes a row dearer: 70% of the others' height
+      // (8192^2 star, 12 steps: 3894 GStencil/s at 100%, 4029 at 85%, 4140
+      // at 75% and at 65%); STENCIL_TB_EDGE_PCT sets another percentage
+      static const int pct = [] {
+        const char *e = std::getenv("STENCIL_TB_EDGE_PCT");
+        return e ? std::max(10, std::min(100, std::atoi(e))) : 70;
+      }();
+      const int pair = 2 * S;
+      int by_m = std::max(by * pct / 100, 4 * K * R);
+      by_m += (pair - (by_m + 2 * K * R) % pair) % pair;
+      tl = TbTiling{tiles_x, by, mx0, mx1, std::min(by_m, ny), 1};
+      tl.tiles_y_m = (ny + tl.by_m - 1) / tl.by_m;
+    }
+  }
+  const int ncm = tl.mx0 + (tiles_x - tl.mx1);
+  const int64_t blocks = (int64_t)ncm * tl.tiles_y_m + (int64_t)(tl.mx1 - tl.mx0) * ((ny + by - 1) / by);
   if (blocks > (1LL << 31) - 1) return hipErrorNotSupported;
   const int4 zbox = {L.zbox[0], L.zbox[1], L.zbox[2], L.zbox[3]};
   if (L.zb)
     hipLaunchKernelGGL((k_sweep2d_tb<T, R, MASK, K, true>), dim3((unsigned)blocks), dim3(64), 0,
-                       L.stream, (const T *)L.in, (T *)L.out, ny, nx, by, tiles_x, W, zbox,
-                       (T)L.zval);
+                       L.stream, (const T *)L.in, (T *)L.out, ny, nx, tl, W, zbox, (T)L.zval);
   else
     hipLaunchKernelGGL((k_sweep2d_tb<T, R, MASK, K, false>), dim3((unsigned)blocks), dim3(64), 0,
-                       L.stream, (const T *)L.in, (T *)L.out, ny, nx, by, tiles_x, W, zbox, T(0));
+                       L.stream, (const T *)L.in, (T *)L.out, ny, nx, tl, W, zbox, T(0));
   return hipGetLastError();
 }
 
