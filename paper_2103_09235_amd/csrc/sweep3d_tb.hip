@@ -86,11 +86,16 @@ struct Geo {
   static constexpr int CW(int s) { return (kTX + 2 * B(s)) / 4; }  // runs per row
   static constexpr int C(int s) { return CW(s) * (TY + 2 * H(s)); }  // runs
   static constexpr int NC(int s) { return (C(s) + kThreads - 1) / kThreads; }
-  // LDS plane: level 0's region plus a margin of 4 columns and R rows on
-  // each side (reads of the outermost runs stay inside the plane)
-  static constexpr int XOFF = B(0) + 4;
+  // LDS plane: level 0's region plus R rows on each side, rows packed with
+  // no column margin: consecutive runs of a wavefront that cross to the next
+  // row stay 4 columns apart, so a 16-lane group of a 16-byte access never
+  // meets the same bank twice (a margin made each such crossing a bank
+  // conflict).  The outermost runs of a level s >= 1 read the adjacent row's
+  // end instead of a margin: that only reaches columns outside the level's
+  // valid width (K-s)R, which B(s) exceeds.
+  static constexpr int XOFF = B(0);
   static constexpr int YOFF = H(0) + R;
-  static constexpr int LW = kTX + 2 * B(0) + 8;
+  static constexpr int LW = kTX + 2 * B(0);
   static constexpr int LH = TY + 2 * H(0) + 2 * R;
   static constexpr int PLANE = LW * LH;
 };
