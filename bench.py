@@ -53,10 +53,6 @@ BF16_MFMA_TFLOPS = 2500.0       # dense BF16 matrix
 FP32_FMA_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 METRIC = "GStencil/s and % HBM roofline, plain vs folded/MFMA/batched at stated error"
 VALU32_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit VALU lane-operations per second (x1e12)
-# fused Game of Life: VALU instructions per wavefront row (64 words of 4
-# cells) and generation, 15.6-16.1 in the gfx950 assembly of the loop (16
-# and 4 generations per launch)
-LIFE_VALU_PER_ROW_GEN = 16.0
 DEFAULT_SET = ("star2d", "heat1d", "star3d", "box3d", "box2d", "batched")
 GATE = {"vector": 0.0, "vector_graph": 0.0, "vector_unfused": 0.0, "symmetric": 1e-5,
         "separable": 1e-5, "mfma_bf16x3": 1e-3}
@@ -120,6 +116,7 @@ KERNEL_SOURCES = {
     "sweep3dtb": ("sweep3d_tb.hip",),
     "sweep3dsep": ("sweep3d_sep.hip",),
     "mfma2d": ("mfma2d.hip",),
+    "life": ("life.hip",),
     "batched": ("batched.hip", "sweep2d_common.h", "sweep2d_impl.h"),
 }
 
@@ -816,19 +813,24 @@ def bench_life(args):
     cells.copy_(torch.from_numpy(g0).to(dev))
     sf.stencil_life(cells, scratch, 4)
     ok = bool(np.array_equal(cells.cpu().numpy(), oracle.life(g0, 4)))
-    # Integer VALU work: each lane (one 4-cell word) executes about
-    # LIFE_VALU_PER_ROW_GEN instructions per generation, priced against the
-    # 32-bit VALU issue rate (useful cells only, not the strips' borders).
+    # Integer VALU work: the wavefront VALU instructions one launch issues
+    # (rocprofv3 SQ_INSTS_VALU of the fused kernel, from the committed
+    # counter summary while life.hip is unchanged), 64 lanes each, priced
+    # against the 32-bit VALU issue rate; the issue includes the strips'
+    # discarded border work.
     gens = T / launches
     dur = launch_ms / 1e3
-    ops = LIFE_VALU_PER_ROW_GEN * (n / 4) * gens  # lane-operations
-    roof = {"bound": "alu", "achieved": round(ops / dur / 1e12, 2),
+    insts = traffic_from_profiles("life", "life2d", field="valu-insts-per-launch")
+    achieved = round(insts * 64 / dur / 1e12, 2) if insts else None
+    roof = {"bound": "alu", "achieved": achieved,
             "peak": VALU32_TOPS, "unit": "Tlane-op/s",
             "peak_basis": "32-bit VALU issue: 256 CUs x 64 lanes x 2.4 GHz",
+            "achieved_basis": ("rocprofv3 SQ_INSTS_VALU per launch x 64 lanes / launch duration "
+                               "(profiles/life_life2d_pmc.txt)"),
             "kernel": "k_life_tb (%.2f generations per launch)" % gens,
             "launch_ms": round(launch_ms, 5), "algorithmic_bytes_per_launch": 2 * n,
             "hbm_frac": round(2 * n / dur / 1e9 / HBM_PEAK_GBS, 4), "traffic": None}
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["frac"] = round(achieved / roof["peak"], 4) if achieved else None
     res = {"metric": METRIC, "value": round(gst, 2), "unit": "GStencil/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(el / args.steps * 1e3, 4), "higher_is_better": True,
