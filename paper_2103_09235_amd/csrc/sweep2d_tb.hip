@@ -123,7 +123,7 @@ __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict_
 
   const int lane = threadIdx.x;
   const int xo0 = tx * WOUT;     // first stored column of the strip
-  const int xi0 = xo0 - B;       // first loaded column (a multiple of 4)
+  const int xi0 = xo0 - B;       // first loaded column (a multiple of kVX)
   const int jstart = y0 - K * R, jend = y1 + K * R;  // level-0 rows streamed
   // The lane's columns xi0 + kVX*lane .. + kVX - 1 wrap as a whole (nx % kVX == 0).
   const int gx = wrap1(xi0 + kVX * lane, nx);
@@ -202,7 +202,9 @@ __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict_
         }
       }
     }
-    const int yd = j - K * R;  // level-K row just completed (all stages ran)
+    // level-K row just completed; a stored row has j - jstart >= 2KR, where
+    // every stage runs
+    const int yd = j - K * R;
     if (store_ok && yd >= y0 && yd < y1) store_vec<T, kVX>(out + (size_t)yd * nx + xo0 + lo, cur);
   };
 
