@@ -254,9 +254,15 @@ k_sweep3d_tb(const float *__restrict__ in, float *__restrict__ out, int nz, int 
             for (int ox = -R; ox <= R; ++ox) {
               if (in_mask<MASK, R>(oz, oy, ox)) {
                 const float w = W.v[((oz + R) * S + (oy + R)) * S + (ox + R)];
+                // an output plane's first tap (oz = -R, then the lowest oy
+                // and ox of that plane's taps) starts its sum from +0, in
+                // place of a slot cleared after the plane before
+                constexpr int O1 = MASK == MASK_BOX ? -R : 0;
+                const bool first = k == S - 1 && oy == O1 && ox == O1;
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                  acc[s][slot][i][v] = __builtin_fmaf(w, seg[4 + v + ox], acc[s][slot][i][v]);
+                  acc[s][slot][i][v] =
+                      __builtin_fmaf(w, seg[4 + v + ox], first ? 0.0f : acc[s][slot][i][v]);
               }
             }
           }
@@ -292,10 +298,6 @@ k_sweep3d_tb(const float *__restrict__ in, float *__restrict__ out, int nz, int 
           }
         }
       }
-#pragma unroll
-      for (int i = 0; i < G::NC(s); ++i)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[s][u][i][v] = 0.0f;
     });
   };
   // whole rounds of NU steps without a branch, then the last steps
