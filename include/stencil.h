@@ -161,7 +161,7 @@ int stencil_plan_set_mode(stencil_plan p, int mode);
  * radius 1-4, FP64 radius 1-2, up to 12 steps for radius-1 stars; rows of
  * whole 16-byte vectors, at least 256 FP32 or 128 FP64 columns) fuse steps
  * in registers; the 3D FP32 VECTOR kernels (the radius-1
- * star up to 4 steps, the radius-1 box 2, the folded star of radius 2 two
+ * star 3 steps, the radius-1 box 2, the folded star of radius 2 two
  * applications) stream them through LDS pipeline stages.  Either way the
  * result equals one launch per application bit for bit.  0 = the library's
  * choice (default), 1 = one application per launch, k > 1 = at most k.

@@ -362,7 +362,7 @@ hipError_t launch_v(const SweepLaunch &L) {
 int tb3_max(int R, int mask) {
   static const int star_k = [] {
     const char *e = std::getenv("STENCIL_TB3_STAR_K");
-    return e ? std::max(1, std::min(4, std::atoi(e))) : 4;
+    return e ? std::max(1, std::min(4, std::atoi(e))) : 3;
   }();
   if (R == 1) return mask == MASK_BOX ? 2 : star_k;
   // the folded 7-point star (25-point diamond); the folded 27-point box (125
@@ -382,11 +382,12 @@ int sweep3d_max_steps(const SweepLaunch &L) {
   return std::max(1, K);
 }
 
-// Tile heights measured at 512^3 (the alternative in brackets): 7-point
-// star, 4 steps per launch, 16 rows: 1251 GStencil/s (32: 1044); folded star
-// (25-point diamond), 2 applications, 16 rows: 1532 (32: 1403); 27-point
-// box, 2 steps, 32 rows: 827 (16: 788).  Taller tiles repeat less border
-// work but hold more LDS per workgroup, so fewer workgroups share a CU.
+// Tile heights and depths measured at 512^3 (the alternatives in brackets):
+// 7-point star, 3 steps per launch, 16 rows: 1680-1695 GStencil/s (32 rows:
+// 1607; 4 steps: 1492, 2 steps: 1188); folded star (25-point diamond), 2
+// applications, 16 rows: 1545-1591 (32: 1465); 27-point box, 2 steps, 32
+// rows: 840-846 (16: 786).  Taller tiles repeat less border work but hold
+// more LDS per workgroup, so fewer workgroups share a CU.
 hipError_t launch_sweep3d_tb(const SweepLaunch &L) {
   if (L.steps < 2 || L.steps > sweep3d_max_steps(L)) return hipErrorNotSupported;
   const int R = L.op->R;

@@ -248,7 +248,7 @@ def test_run_schedule_counts_launches():
     assert (s["plain_launches"], s["final_copy"]) == (4, False)
     star3 = sf.Plan(synth.WORKLOADS["star3d"].weights, sf.STENCIL_STAR)
     s = _sched(star3, (512, 512, 512), 200)
-    assert (s["plain_launches"], s["final_copy"]) == (50, False)
+    assert (s["plain_launches"], s["final_copy"]) == (68, False)  # 3 steps per launch at most
     assert _sched(star3, (512, 512, 512), 200, sf.STENCIL_F64)["plain_launches"] == 200
     assert _sched(star3, (8, 512, 512), 8)["plain_launches"] == 4  # three per launch at most
     assert _sched(star3, (4, 512, 512), 4)["plain_launches"] == 4  # one per launch
