@@ -71,8 +71,9 @@ def run(w, kind, u0, T, m, mode=sf.STENCIL_MODE_VECTOR):
     # the headline launch geometry: two fused launches of 12 steps each
     # (strip height from the occupancy query), and the plain 7-point 3D star
     ("star2d", 1, 24, "vector"), ("star3d", 1, 3, "vector"),
-    # 3D fused launches as the 512^3 runs make them: four steps of the
-    # 7-point star, two of the 27-point box
+    # 3D fused launches beside those the 512^3 runs make: four steps of the
+    # 7-point star (a fused launch of three, then one plain step; four per
+    # launch where STENCIL_TB3_STAR_K asks for them), two of the 27-point box
     ("star3d", 1, 4, "vector"), ("box3d", 1, 4, "vector"),
 ])
 def test_sampled_outputs_full_size(name, m, T, mode):
