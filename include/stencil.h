@@ -374,7 +374,7 @@ int stencil_residual(const void *u, const void *ref, int dtype, int64_t n,
  * is looked up on the first call on each device.  The reduction tree is the
  * one stencil_residual uses, so the results are bit-identical to it.
  * Errors: E_ARG, E_UNSUPPORTED (partials larger than the array: never with
- * this build's constants), E_DEVICE.
+ * the library's compiled-in sizes), E_DEVICE.
  */
 int stencil_residual_noalloc(const void *u, const void *ref, int dtype, int64_t n,
                              void *stream, double *out_dev);
