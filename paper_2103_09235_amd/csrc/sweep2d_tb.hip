@@ -88,6 +88,34 @@ __device__ __forceinline__ double lane_from_right(double x) {
       __builtin_amdgcn_update_dpp(0, h.y, 0x130, 0xF, 0xF, true)));
 }
 
+// acc + w * (a neighbouring lane's x), the lane shift done by the FMA's own
+// DPP source operand (lanes at the wavefront's end read 0, as above).  The
+// compiler folds a DPP move into adds and multiplies but not into an FMA with
+// an accumulator, and it cannot see the DPP read inside the asm: the s_nop
+// gives the two wait states a DPP read needs after a VALU write of its
+// source.  FIRST: the sum starts from +0 (acc is not read).
+template <bool LEFT, bool FIRST>
+__device__ __forceinline__ float fma_lane(float x, float w, float acc) {
+  if constexpr (FIRST) {
+    float r;
+    if constexpr (LEFT)
+      asm("s_nop 1\n\tv_mov_b32 %0, 0\n\tv_fmac_f32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf "
+          "bank_mask:0xf bound_ctrl:1" : "=&v"(r) : "v"(x), "v"(w));
+    else
+      asm("s_nop 1\n\tv_mov_b32 %0, 0\n\tv_fmac_f32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf "
+          "bank_mask:0xf bound_ctrl:1" : "=&v"(r) : "v"(x), "v"(w));
+    return r;
+  } else {
+    if constexpr (LEFT)
+      asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf "
+          "bound_ctrl:1" : "+v"(acc) : "v"(x), "v"(w));
+    else
+      asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf "
+          "bound_ctrl:1" : "+v"(acc) : "v"(x), "v"(w));
+    return acc;
+  }
+}
+
 template <typename F, int... Ks>
 __device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Ks...>) {
   (f(std::integral_constant<int, Ks>{}), ...);
@@ -140,6 +168,23 @@ __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict_
   // most strips hold no pad column: their rows are masked whole (uniform)
   const bool cols_in = !ZB || (xi0 >= zbox.z && xi0 + kSpan <= zbox.w);
 
+  // FP32 radius 1: the lane shifts are done by the FMAs' own DPP source
+  // operands (at larger radii the waits they need cost more than the moves
+  // they save); the weights of those taps in VGPRs (an operand beside a DPP
+  // source must be one)
+  constexpr bool kDppFma = sizeof(T) == 4 && R == 1;
+  T wv[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) {
+    if constexpr (kDppFma) {
+      float r;
+      asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(W[i]));
+      wv[i] = r;
+    } else {
+      wv[i] = W[i];
+    }
+  }
+
   T acc[K][NU][kVX];
 #pragma unroll
   for (int s = 0; s < K; ++s)
@@ -164,14 +209,17 @@ __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict_
 #pragma unroll
     for (int s = 0; s < (NA < 0 ? K : NA); ++s) {
       if (PRO && j - jstart < 2 * s * R) break;  // uniform: later stages start later
-      // the R columns on either side come from the neighbouring lanes
+      // the R columns on either side come from the neighbouring lanes (FP32
+      // radius 1: read by the FMAs themselves)
       T win[kVX + 2 * R];
 #pragma unroll
-      for (int i = 0; i < R; ++i) win[i] = lane_from_left(cur[kVX - R + i]);
+      for (int i = 0; i < R; ++i)
+        win[i] = kDppFma ? T(0) : lane_from_left(cur[kVX - R + i]);
 #pragma unroll
       for (int v = 0; v < kVX; ++v) win[R + v] = cur[v];
 #pragma unroll
-      for (int i = 0; i < R; ++i) win[R + kVX + i] = lane_from_right(cur[i]);
+      for (int i = 0; i < R; ++i)
+        win[R + kVX + i] = kDppFma ? T(0) : lane_from_right(cur[i]);
       // input row j feeds output rows j-R+k with vertical offset oy = R-k;
       // for each output row the offsets arrive with oy ascending, and the
       // first one (k = 2R) starts the sum from +0 in place of a cleared slot
@@ -185,8 +233,22 @@ __device__ __forceinline__ void tb_body(const T *__restrict__ in, T *__restrict_
             const T wt = W[(oy + R) * S + (ox + R)];
             const bool first = k == S - 1 && ox == (MASK == MASK_BOX ? -R : 0);
 #pragma unroll
-            for (int v = 0; v < kVX; ++v)
-              acc[s][slot][v] = fmat(wt, win[R + v + ox], first ? T(0) : acc[s][slot][v]);
+            for (int v = 0; v < kVX; ++v) {
+              const int c = v + ox;  // the tap's column, relative to the lane's first
+              if constexpr (kDppFma) {
+                const T wr = wv[(oy + R) * S + (ox + R)];
+                if (c < 0)
+                  acc[s][slot][v] = first ? fma_lane<true, true>(cur[kVX + c], wr, T(0))
+                                          : fma_lane<true, false>(cur[kVX + c], wr, acc[s][slot][v]);
+                else if (c >= kVX)
+                  acc[s][slot][v] = first ? fma_lane<false, true>(cur[c - kVX], wr, T(0))
+                                          : fma_lane<false, false>(cur[c - kVX], wr, acc[s][slot][v]);
+                else
+                  acc[s][slot][v] = fmat(wt, cur[c], first ? T(0) : acc[s][slot][v]);
+              } else {
+                acc[s][slot][v] = fmat(wt, win[R + c], first ? T(0) : acc[s][slot][v]);
+              }
+            }
           }
         }
       }
