@@ -459,7 +459,11 @@ int tb_max(int R, int mask, int dtype) {
     if (R == 1) return mask == MASK_BOX ? 8 : (star1 ? star1 : 12);
     return R == 2 ? 4 : 1;
   }
-  if (R == 1 && mask != MASK_BOX) return star1 ? star1 : 12;
+  // FP32 radius-1 star: 10 steps, where the kernel (149 VGPRs) holds three
+  // wavefronts per SIMD; 12 need 186 and allow two (8192^2 on one GPU: 5155
+  // GStencil/s at 10 against 5064 at 12, the zero-boundary star 4488 against
+  // 4222; 11 capped to three wavefronts spills, 12 capped spills more)
+  if (R == 1 && mask != MASK_BOX) return star1 ? star1 : 10;
   return R == 1 ? 8 : R == 2 ? 4 : R <= 4 ? 2 : 1;
 }
 

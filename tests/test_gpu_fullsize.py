@@ -68,9 +68,9 @@ def run(w, kind, u0, T, m, mode=sf.STENCIL_MODE_VECTOR):
     ("box2d", 4, 8, "vector"), ("box2d", 8, 8, "vector"), ("box2d", 4, 8, "mfma"),
     ("box2d", 8, 16, "mfma"), ("star3d", 2, 4, "vector"), ("box3d", 2, 4, "vector"),
     ("box3d", 1, 3, "vector"), ("unitbox2d", 8, 16, "separable"), ("box2d", 1, 16, "vector"),
-    # the headline launch geometry: two fused launches of 12 steps each
+    # the headline launch geometry: two fused launches of 10 steps each
     # (strip height from the occupancy query), and the plain 7-point 3D star
-    ("star2d", 1, 24, "vector"), ("star3d", 1, 3, "vector"),
+    ("star2d", 1, 20, "vector"), ("star3d", 1, 3, "vector"),
     # 3D fused launches beside those the 512^3 runs make: four steps of the
     # 7-point star (a fused launch of three, then one plain step; four per
     # launch where STENCIL_TB3_STAR_K asks for them), two of the 27-point box
@@ -242,13 +242,13 @@ def test_dirichlet_sampled_outputs_full_size():
 
 
 def test_dirichlet_plain_fused_full_size():
-    """Zero boundaries, plain sweep at the measured size (8192^2, T = 24: two
-    launches of 12 fused steps on the padded grid): sampled points, corners
+    """Zero boundaries, plain sweep at the measured size (8192^2, T = 20: two
+    launches of 10 fused steps on the padded grid): sampled points, corners
     and edges included, against the FP64 zero-ghost oracle on the point's
     window clipped to the grid."""
     wl = synth.WORKLOADS["star2d_dirichlet"]
     u0 = full_grid("star2d")
-    T = 24
+    T = 20
     plan = sf.Plan(wl.weights, wl.shape_kind, sf.STENCIL_DIRICHLET)
     d = torch.from_numpy(u0).to(DEV)
     sched = plan.schedule(d, T)
