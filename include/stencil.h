@@ -158,7 +158,7 @@ int stencil_plan_set_mode(stencil_plan p, int mode);
  * stencil_plan_set_fusion -- the most operator applications one launch may
  * fuse (temporal blocking: Section 3.4 keeps several time steps of a tile on
  * chip between loads).  The 1D kernels and the 2D VECTOR kernels (FP32
- * radius 1-4, FP64 radius 1-2; radius-1 stars up to 10 steps in FP32, 12 in
+ * radius 1-4, FP64 radius 1-2; radius-1 stars up to 10 steps in FP32, 14 in
  * FP64, radius-1 boxes up to 8; rows of
  * whole 16-byte vectors, at least 256 FP32 or 128 FP64 columns) fuse steps
  * in registers; the 3D FP32 VECTOR kernels (the radius-1

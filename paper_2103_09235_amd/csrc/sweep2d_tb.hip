@@ -453,17 +453,20 @@ int tb_max(int R, int mask, int dtype) {
   if (mask == MASK_BOX && R >= 3) return 1;
   static const int star1 = [] {
     const char *e = std::getenv("STENCIL_TB_STAR_K");
-    return e ? std::max(2, std::min(12, std::atoi(e))) : 0;
+    return e ? std::max(2, std::min(14, std::atoi(e))) : 0;
   }();
   if (dtype == STENCIL_F64) {
-    if (R == 1) return mask == MASK_BOX ? 8 : (star1 ? star1 : 12);
+    // the FP64 star: 14 steps (8192^2: 2939 GStencil/s against 2832 at 12,
+    // 2880 at 13; 15 and 16 exceed the registers of two wavefronts per SIMD:
+    // 2664, 2658)
+    if (R == 1) return mask == MASK_BOX ? 8 : (star1 ? star1 : 14);
     return R == 2 ? 4 : 1;
   }
   // FP32 radius-1 star: 10 steps, where the kernel (149 VGPRs) holds three
   // wavefronts per SIMD; 12 need 186 and allow two (8192^2 on one GPU: 5155
   // GStencil/s at 10 against 5064 at 12, the zero-boundary star 4488 against
   // 4222; 11 capped to three wavefronts spills, 12 capped spills more)
-  if (R == 1 && mask != MASK_BOX) return star1 ? star1 : 10;
+  if (R == 1 && mask != MASK_BOX) return star1 ? std::min(star1, 12) : 10;
   return R == 1 ? 8 : R == 2 ? 4 : R <= 4 ? 2 : 1;
 }
 
@@ -480,7 +483,7 @@ hipError_t launch_t(const SweepLaunch &L) {
     }
   } else {
     switch (L.op->R) {
-      case 1: return box ? launch_upto<T, 1, MASK_BOX, 8>(L) : launch_upto<T, 1, MASK_DIAMOND, 12>(L);
+      case 1: return box ? launch_upto<T, 1, MASK_BOX, 8>(L) : launch_upto<T, 1, MASK_DIAMOND, 14>(L);
       case 2: return box ? launch_upto<T, 2, MASK_BOX, 4>(L) : launch_upto<T, 2, MASK_DIAMOND, 4>(L);
       default: return hipErrorNotSupported;
     }

@@ -195,7 +195,7 @@ def test_run_schedule_counts_launches():
     s = _sched(star, (8192, 8192), 1)
     assert (s["plain_launches"], s["final_copy"]) == (1, True)
     # rows that are not whole 16-byte vectors, narrow grids, unaligned
-    # buffers: one step per launch; FP64 grids up to 12 steps (radius-1 star)
+    # buffers: one step per launch; FP64 grids up to 14 steps (radius-1 star)
     assert _sched(star, (8192, 8191), 10)["plain_launches"] == 10
     assert _sched(star, (64, 252), 10)["plain_launches"] == 10
     assert _sched(star, (512, 512), 12, sf.STENCIL_F64)["plain_launches"] == 2
@@ -221,8 +221,8 @@ def test_run_schedule_counts_launches():
     assert (s["plain_launches"], s["final_copy"]) == (2, True)
     assert _sched(dstar, (1, 2), 3)["plain_launches"] == 3
     assert _sched(dstar, (100, 100), 10)["plain_launches"] == 10
-    assert _sched(dstar, (8192, 8192), 12, sf.STENCIL_F64)["plain_launches"] == 1
-    assert _sched(dstar, (8192, 8192), 13, sf.STENCIL_F64)["plain_launches"] == 2
+    assert _sched(dstar, (8192, 8192), 14, sf.STENCIL_F64)["plain_launches"] == 1
+    assert _sched(dstar, (8192, 8192), 15, sf.STENCIL_F64)["plain_launches"] == 2
     # boxes of radius 3 and more are not fused (FMA-issue bound already)
     b3 = synth.random_positive_weights(2, 3)
     assert _sched(sf.Plan(b3, sf.STENCIL_BOX), (8192, 8192), 10)["plain_launches"] == 10

@@ -402,10 +402,10 @@ TB_CASES = [
     # `fusion` steps (0 = library choice); shapes span several 256-column
     # strips with a ragged last strip, and the minimum row count 2KR+1
     ("star_r1_k8", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (200, 1000), 16, 1, 8),
-    ("star_r1_k12", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (200, 1000), 24, 1, 0),
+    ("star_r1_k10", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (200, 1000), 20, 1, 0),
     ("star_r1_k10_k11", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (90, 1284), 42, 1, 11),
     ("star_r1_k9_k10", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (64, 772), 38, 1, 10),
-    ("star_r1_k12_min_rows", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (25, 512), 24, 1,
+    ("star_r1_k10_min_rows", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (21, 512), 20, 1,
      0),
     ("star_r1_min_rows", synth.WORKLOADS["star2d"].weights, sf.STENCIL_STAR, (17, 256), 8, 1, 8),
     ("box_r1_k7", synth.WORKLOADS["box2d"].weights, sf.STENCIL_BOX, (150, 772), 14, 1, 7),
@@ -498,7 +498,7 @@ def test_separable_3d(case):
 
 TB64_CASES = [
     # (name, weights, kind, shape, T, m, fusion, boundary): FP64 2D grids
-    ("star_r1_k12", synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR, (150, 772), 25, 1, 0,
+    ("star_r1_k14", synth.star2d_weights(0.6, 0.1), sf.STENCIL_STAR, (150, 772), 28, 1, 0,
      "periodic"),
     ("box_r1_k8", synth.random_positive_weights(2, 1), sf.STENCIL_BOX, (99, 516), 17, 1, 0,
      "periodic"),
